@@ -1,0 +1,138 @@
+"""Seeded synthetic inputs for the Sprintz codec (tests and benchmark).
+
+This module holds no codec arithmetic: it only draws the integer time series
+that both the CPU oracle and the GPU library are fed. The paper's own speed
+experiments use synthetic data too (Section 5.3: uniform random values at
+full range); the shaped generators below mimic sensor streams -- random
+walks, stationary AR(2) columns and constant runs -- because the datasets of
+the paper's ratio experiments (UCR, PAMAP, MSRC-12, UCI Gas, AMPDs) are not
+available here. Every generator is a pure function of its seed.
+
+Workloads (sizes as in the benchmark configuration list):
+  * ``walk_int8``   -- 65,536 x 1 int8 random walk, N(0, 2) integer steps,
+                       clipped to [-128, 127], 15 % of samples in constant runs
+                       of 8..256 rows; seed 0.
+  * ``ar2_uint16``  -- 4,194,304 x 8 uint16, each column AR(2) with
+                       coefficients (1.6, -0.7) and N(0, 20) noise, offset
+                       32768 and clipped; 20 % of rows in flat runs of 8..256
+                       rows in which every column repeats the previous row;
+                       seed 1.
+  * ``batch_stream``-- one stream of the 10,000-stream batch (seed 2e6 + k).
+  * ``laplace_walk_uint16`` -- D=4 uint16 walks with Laplace(0, 3) steps,
+                       wrapping modulo 2^16 (the Huffman workload); seed 3.
+  * ``uniform``     -- full-range uniform values (the paper's speed workload).
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.signal import lfilter
+
+
+def _run_mask(rng: np.random.Generator, n: int, coverage: float, lo: int = 8, hi: int = 256) -> np.ndarray:
+    """Boolean mask of length n made of runs of U{lo..hi} positions, added
+    at uniform random starts until at least ``coverage`` of n is covered."""
+    mask = np.zeros(n, dtype=bool)
+    if n == 0 or coverage <= 0:
+        return mask
+    target = coverage * n
+    covered = 0
+    while covered < target:
+        L = int(rng.integers(lo, hi + 1))
+        L = min(L, n)
+        s = int(rng.integers(0, n - L + 1))
+        before = int(mask[s:s + L].sum())
+        mask[s:s + L] = True
+        covered += L - before
+    return mask
+
+
+def clipped_walk(start: int, steps: np.ndarray, lo: int, hi: int) -> np.ndarray:
+    """x_t = clip(x_{t-1} + steps_t, lo, hi), x_{-1} = start, along axis 0.
+
+    The map y -> clip(y + a, lo, hi) composes into maps of the same form
+    y -> min(max(y + A, B), C), so the recursion is evaluated with a
+    log-step prefix composition (exact integers, vectorised)."""
+    steps = np.asarray(steps, dtype=np.int64)
+    A = steps.copy()
+    B = np.full_like(A, lo)
+    C = np.full_like(A, hi)
+    n = A.shape[0]
+    k = 1
+    while k < n:
+        # compose earlier map (t-k) then later map (t) for t >= k
+        a1, b1, c1 = A[:-k], B[:-k], C[:-k]
+        a2, b2, c2 = A[k:], B[k:], C[k:]
+        nA = a1 + a2
+        nC = np.minimum(np.maximum(c1 + a2, b2), c2)
+        nB = np.minimum(np.maximum(b1 + a2, b2), nC)
+        A = np.concatenate([A[:k], nA])
+        B = np.concatenate([B[:k], nB])
+        C = np.concatenate([C[:k], nC])
+        k *= 2
+    return np.minimum(np.maximum(start + A, B), C)
+
+
+def walk_int8(rows: int = 65536, D: int = 1, sigma: float = 2.0, const_frac: float = 0.15,
+              seed: int = 0) -> np.ndarray:
+    """int8 random walk from 0 with rint(N(0, sigma)) steps clipped to the
+    int8 range; ``const_frac`` of the rows lie in constant runs."""
+    rng = np.random.default_rng(seed)
+    inc = np.rint(rng.normal(0.0, sigma, size=(rows, D))).astype(np.int64)
+    mask = _run_mask(rng, rows, const_frac)
+    inc[mask] = 0
+    x = clipped_walk(0, inc, -128, 127)
+    return x.astype(np.int8)
+
+
+def ar2_uint16(rows: int = 4194304, D: int = 8, sigma: float = 20.0, flat_frac: float = 0.20,
+               seed: int = 1) -> np.ndarray:
+    """uint16 columns y_t = 1.6 y_{t-1} - 0.7 y_{t-2} + N(0, sigma), offset by
+    32768 and clipped; ``flat_frac`` of the rows repeat the previous row in
+    every column."""
+    rng = np.random.default_rng(seed)
+    noise = rng.normal(0.0, sigma, size=(rows, D))
+    y = lfilter([1.0], [1.0, -1.6, 0.7], noise, axis=0)
+    x = np.clip(np.rint(y) + 32768, 0, 65535).astype(np.uint16)
+    mask = _run_mask(rng, rows, flat_frac)
+    src = np.where(mask, 0, np.arange(rows))
+    src = np.maximum.accumulate(src) if rows else src
+    return np.ascontiguousarray(x[src])
+
+
+def uniform(rows: int, D: int, dtype, seed: int = 5) -> np.ndarray:
+    """Full-range uniform values: the paper's incompressible speed workload."""
+    rng = np.random.default_rng(seed)
+    info = np.iinfo(dtype)
+    return rng.integers(info.min, info.max + 1, size=(rows, D), dtype=np.int64).astype(dtype)
+
+
+def laplace_walk_uint16(rows: int, D: int = 4, scale: float = 3.0, seed: int = 3) -> np.ndarray:
+    """uint16 walks from 32768 with rint(Laplace(0, scale)) steps, wrapping
+    modulo 2^16."""
+    rng = np.random.default_rng(seed)
+    inc = np.rint(rng.laplace(0.0, scale, size=(rows, D))).astype(np.int64)
+    x = (32768 + np.cumsum(inc, axis=0)) % 65536
+    return x.astype(np.uint16)
+
+
+def batch_stream_params(k: int) -> tuple[int, int, np.dtype, float]:
+    """(rows, D, dtype, sigma) of stream k of the batch workload: rows
+    log-uniform in [1e3, 1e6), D uniform in {1,2,4,8,16}, even k int8 and odd
+    k uint16, noise sigma log-uniform in [0.5, 200)."""
+    rng = np.random.default_rng(2_000_000 + k)
+    rows = int(np.floor(np.exp(rng.uniform(np.log(1e3), np.log(1e6)))))
+    D = int(rng.choice([1, 2, 4, 8, 16]))
+    sigma = float(np.exp(rng.uniform(np.log(0.5), np.log(200.0))))
+    dt = np.dtype(np.int8) if k % 2 == 0 else np.dtype(np.uint16)
+    return rows, D, dt, sigma
+
+
+def batch_stream(k: int, max_rows: int | None = None) -> np.ndarray:
+    """Stream k of the batch workload (generators of the two single-stream
+    workloads with the stream's own sigma). ``max_rows`` truncates."""
+    rows, D, dt, sigma = batch_stream_params(k)
+    if max_rows is not None:
+        rows = min(rows, max_rows)
+    if dt == np.int8:
+        return walk_int8(rows, D, sigma=sigma, seed=3_000_000 + k)
+    return ar2_uint16(rows, D, sigma=sigma, seed=3_000_000 + k)
