@@ -1,0 +1,132 @@
+/*
+ * sprintz.h -- C ABI of the MI355X (gfx950) Sprintz codec.
+ *
+ * Sprintz (Blalock, Madden & Guttag, IMWUT 2018) compresses a multivariate
+ * integer time series: T samples (rows) of D columns, every element an
+ * integer of bitwidth w = 8 or 16 stored row-major (Section 3.1,
+ * Definitions). Per column a forecaster predicts each sample (delta coding,
+ * Section 4.2.1, or FIRE, Section 4.2.2 / Algorithm 3); the errors are
+ * zigzag coded, every block of 8 rows gets one bit width per column, the
+ * block is bit packed behind a header of log2(w)-bit width codes, and runs of
+ * all-zero blocks become a single run-length record (Algorithm 1, Section
+ * 4.3). Decompression inverts this (Algorithm 2).
+ *
+ * For parallelism the series is cut into independently coded segments of
+ * seg_rows rows; every segment restarts the forecaster state at zero, exactly
+ * as the paper starts a stream. The container is self-describing:
+ *
+ *   64-byte header | (nseg+1) x u64 segment offsets | pad to 16 | segments
+ *   segment = u32 nrec | header groups | raw tail rows | pad to 16
+ *
+ * Conventions for every entry point below:
+ *   - Pointers named d_* are device pointers (HIP global memory) on the
+ *     current device; h_* are host pointers. The caller owns every buffer;
+ *     the library never allocates, frees or retains caller memory.
+ *   - Work is enqueued on `stream` and is asynchronous; nothing is
+ *     synchronised. Host-detectable argument errors are returned at once
+ *     and then nothing is enqueued.
+ *   - Device-detected problems (a corrupt container, an internal size
+ *     mismatch) are ORed into *d_status as nonzero bits; *d_status must be 0
+ *     on entry and may be NULL to skip device-side reporting. The kernels
+ *     never trap and never write outside [d_dst, d_dst + dst_cap).
+ *   - int8/uint8 (and int16/uint16) produce identical bytes: the codec works
+ *     on w-bit patterns modulo 2^w. The dtype is recorded only so that the
+ *     decoder can report it.
+ *   - GPU limits: 1 <= D <= 64, 8 <= seg_rows <= 2^20 with seg_rows % 8 == 0,
+ *     hdr_group <= 255, learn_shift <= 8. Outside them the call returns
+ *     SPZ_EUNSUPPORTED (D) or SPZ_EINVAL (the rest).
+ */
+#ifndef SPRINTZ_H_
+#define SPRINTZ_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPZ_OK = 0,
+    SPZ_EINVAL = -1,        /* bad argument */
+    SPZ_ENOSPC = -2,        /* destination or workspace too small */
+    SPZ_ECORRUPT = -3,      /* container header invalid */
+    SPZ_EUNSUPPORTED = -4,  /* valid request outside the GPU limits */
+    SPZ_EHIP = -5,          /* a HIP runtime call failed */
+    SPZ_ENOMEM = -6
+} spz_status;
+
+typedef enum { SPZ_INT8 = 1, SPZ_UINT8 = 2, SPZ_INT16 = 3, SPZ_UINT16 = 4 } spz_dtype;
+
+/* Section 4.2: delta coding or FIRE (Fast Integer REgression). */
+typedef enum { SPZ_DELTA = 0, SPZ_FIRE = 1 } spz_forecaster;
+
+typedef struct {
+    uint32_t struct_size;  /* sizeof(spz_params) */
+    uint32_t forecaster;   /* spz_forecaster */
+    uint32_t seg_rows;     /* rows per independently coded segment (multiple of 8) */
+    uint32_t hdr_group;    /* records whose headers are stored together (Section 4.3,
+                              last paragraph); 0 = one group per segment */
+    uint32_t learn_shift;  /* FIRE learning rate eta = 2^-learn_shift (paper: eta = 1/2) */
+    uint32_t entropy;      /* 0 = no entropy stage (the only value accepted) */
+} spz_params;
+
+typedef struct {
+    uint64_t rows;
+    uint32_t D;
+    uint32_t dtype;             /* spz_dtype */
+    spz_params params;
+    uint64_t compressed_size;   /* total container bytes */
+    uint64_t decompressed_size; /* rows * D * (w / 8) */
+    uint32_t nseg;
+    uint32_t w;                 /* 8 or 16 */
+} spz_info;
+
+/* Fill *p with the defaults: FIRE, seg_rows 1024, hdr_group 0, learn_shift 1,
+ * entropy 0. */
+void spz_params_default(spz_params *p);
+
+/* Largest container sprintz_compress can write for this shape: every block
+ * at full width plus headers, padding and the offset table. 0 if the
+ * arguments are invalid. */
+size_t sprintz_compress_bound(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p);
+
+/* Bytes of device workspace sprintz_compress needs (8 per segment). */
+size_t sprintz_workspace_size(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p);
+
+/* Compress d_src, a row-major (rows, D) array of `dtype` (alignment: the
+ * element size), into the container d_dst (16-byte aligned, dst_cap >=
+ * sprintz_compress_bound). The container's byte count is written to the
+ * device word *d_out_size (required). d_ws (8-byte aligned, ws_size >=
+ * sprintz_workspace_size) holds per-segment sizes between the kernels.
+ * Algorithm 1 (encodeBlock) per block, forecasters of Section 4.2, bit
+ * packing of Section 4.3. */
+spz_status sprintz_compress(const void *d_src, uint64_t rows, uint32_t D, spz_dtype dtype,
+                            const spz_params *p, void *d_dst, size_t dst_cap, uint64_t *d_out_size,
+                            void *d_ws, size_t ws_size, int32_t *d_status, hipStream_t stream);
+
+/* Parse the 64-byte container header from a host copy of at least 64
+ * bytes. SPZ_ECORRUPT if it is not a valid header. */
+spz_status sprintz_get_info(const void *h_src, size_t n, spz_info *out);
+
+/* Decompress the container d_src (16-byte aligned, src_size bytes, described
+ * by *info from sprintz_get_info) into d_dst, a row-major (rows, D) array
+ * (dst_cap >= info->decompressed_size, aligned to the element size).
+ * Algorithm 2 (decodeBlock) per record. Corrupt segments set bit 1 in
+ * *d_status; their output rows are then unspecified. */
+spz_status sprintz_decompress(const void *d_src, size_t src_size, const spz_info *info, void *d_dst,
+                              size_t dst_cap, int32_t *d_status, hipStream_t stream);
+
+/* Static description of a status code. */
+const char *sprintz_strerror(spz_status s);
+
+/* Container format version this library writes and reads (1). */
+int sprintz_format_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPRINTZ_H_ */

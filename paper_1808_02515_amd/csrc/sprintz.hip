@@ -1,0 +1,251 @@
+// Host runtime and C ABI of the gfx950 Sprintz codec (see include/sprintz.h).
+//
+// Compression: pass-1 sizing kernel -> offset-table scan -> pass-2 writing
+// kernel, all on the caller's stream. Decompression: one kernel. The host
+// only validates arguments, derives the launch geometry and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include "sprintz.h"
+#include "spz_decode.h"
+#include "spz_encode.h"
+
+namespace {
+
+constexpr uint32_t kMaxD = 64;
+constexpr uint32_t kMaxSegRows = 1u << 20;
+constexpr size_t kHeader = 64;
+
+uint32_t bits_of(spz_dtype d) {
+    switch (d) {
+        case SPZ_INT8: case SPZ_UINT8: return 8;
+        case SPZ_INT16: case SPZ_UINT16: return 16;
+        default: return 0;
+    }
+}
+
+uint32_t log2_pow2_ceil(uint32_t v) {
+    uint32_t k = 0;
+    while ((1u << k) < v) ++k;
+    return k;
+}
+
+size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
+
+spz_status check_params(const spz_params *p) {
+    if (!p || p->struct_size < sizeof(spz_params)) return SPZ_EINVAL;
+    if (p->forecaster != SPZ_DELTA && p->forecaster != SPZ_FIRE) return SPZ_EINVAL;
+    if (p->seg_rows < 8 || p->seg_rows % 8 != 0 || p->seg_rows > kMaxSegRows) return SPZ_EINVAL;
+    if (p->hdr_group > 255 || p->learn_shift > 8 || p->entropy != 0) return SPZ_EINVAL;
+    return SPZ_OK;
+}
+
+uint64_t num_segments(uint64_t rows, uint32_t S) { return rows == 0 ? 0 : (rows + S - 1) / S; }
+
+spz::Geom make_geom(uint64_t rows, uint32_t D, uint32_t w, uint32_t S, uint32_t G, uint32_t learn_shift) {
+    spz::Geom g;
+    memset(&g, 0, sizeof(g));
+    g.rows = rows;
+    g.D = D;
+    g.S = S;
+    g.nseg = (uint32_t)num_segments(rows, S);
+    g.dp_log2 = log2_pow2_ceil(D);
+    g.G = G;
+    g.sh = learn_shift + 2;
+    g.acc_lo = -(int32_t)((1u << (w - 1)) << g.sh);
+    g.acc_hi = (int32_t)((1u << w) << g.sh);
+    g.data_start = align16(kHeader + 8ull * (g.nseg + 1));
+    return g;
+}
+
+uint32_t grid_for(const spz::Geom &g) {
+    uint64_t lanes = (uint64_t)g.nseg << g.dp_log2;
+    return (uint32_t)((lanes + spz::kThreads - 1) / spz::kThreads);
+}
+
+template <int W, bool FIRE, bool COL>
+hipError_t launch_encode(const void *src, const spz::Geom &g, uint32_t *ws, uint8_t *dst, int32_t *status,
+                         uint32_t dtype, uint32_t forecaster, uint32_t learn_shift, uint64_t *out_size,
+                         hipStream_t stream) {
+    using T = typename spz::Elem<W>::T;
+    const uint32_t grid = grid_for(g);
+    if (grid > 0)
+        hipLaunchKernelGGL((spz::k_encode<W, FIRE, COL, false>), dim3(grid), dim3(spz::kThreads), 0, stream,
+                           (const T *)src, g, ws, dst, status);
+    hipLaunchKernelGGL(spz::k_scan_sizes, dim3(1), dim3(1024), 0, stream, ws, g, (uint32_t)W, dtype, forecaster,
+                       learn_shift, dst, out_size, status);
+    if (grid > 0)
+        hipLaunchKernelGGL((spz::k_encode<W, FIRE, COL, true>), dim3(grid), dim3(spz::kThreads), 0, stream,
+                           (const T *)src, g, ws, dst, status);
+    return hipGetLastError();
+}
+
+template <int W, bool FIRE, bool COL>
+hipError_t launch_decode(const void *src, const spz::Geom &g, void *dst, int32_t *status, hipStream_t stream) {
+    using T = typename spz::Elem<W>::T;
+    const uint32_t grid = grid_for(g);
+    if (grid > 0)
+        hipLaunchKernelGGL((spz::k_decode<W, FIRE, COL>), dim3(grid), dim3(spz::kThreads), 0, stream,
+                           (const uint8_t *)src, g, (T *)dst, status);
+    return hipGetLastError();
+}
+
+uint64_t get_le(const uint8_t *p, int n) {
+    uint64_t v = 0;
+    for (int k = 0; k < n; ++k) v |= (uint64_t)p[k] << (8 * k);
+    return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+void spz_params_default(spz_params *p) {
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(spz_params);
+    p->forecaster = SPZ_FIRE;
+    p->seg_rows = 1024;
+    p->hdr_group = 0;
+    p->learn_shift = 1;
+    p->entropy = 0;
+}
+
+size_t sprintz_compress_bound(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
+    const uint32_t w = bits_of(dtype);
+    if (w == 0 || D == 0 || check_params(p) != SPZ_OK) return 0;
+    const uint32_t hb = w == 8 ? 3 : 4;
+    const uint32_t S = p->seg_rows;
+    const uint64_t nseg = num_segments(rows, S);
+    size_t total = align16(kHeader + 8 * (size_t)(nseg + 1));
+    // all full segments are alike; the last one may be short
+    for (int last = 0; last < 2; ++last) {
+        if (nseg == 0) break;
+        const uint64_t count = last ? 1 : nseg - 1;
+        const uint64_t r = last ? rows - (uint64_t)S * (nseg - 1) : S;
+        const uint64_t nblk = r / 8, tail = r % 8;
+        const uint64_t ngroups = p->hdr_group == 0 ? 1 : (nblk + p->hdr_group - 1) / p->hdr_group;
+        const uint64_t one = 4 + (nblk * D * hb + 7) / 8 + ngroups + nblk * D * w + tail * D * (w / 8) + 15;
+        total += (size_t)(count * one);
+    }
+    return total;
+}
+
+size_t sprintz_workspace_size(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
+    if (bits_of(dtype) == 0 || D == 0 || check_params(p) != SPZ_OK) return 0;
+    return 8 * (size_t)num_segments(rows, p->seg_rows) + 8;
+}
+
+spz_status sprintz_compress(const void *d_src, uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p,
+                            void *d_dst, size_t dst_cap, uint64_t *d_out_size, void *d_ws, size_t ws_size,
+                            int32_t *d_status, hipStream_t stream) {
+    const uint32_t w = bits_of(dtype);
+    if (w == 0 || D == 0) return SPZ_EINVAL;
+    spz_status st = check_params(p);
+    if (st != SPZ_OK) return st;
+    if (D > kMaxD) return SPZ_EUNSUPPORTED;
+    if (num_segments(rows, p->seg_rows) > 0xFFFFFFFFull) return SPZ_EUNSUPPORTED;
+    if (!d_dst || !d_out_size || (rows > 0 && !d_src) || !d_ws) return SPZ_EINVAL;
+    if (((uintptr_t)d_dst & 15) || ((uintptr_t)d_src & (w / 8 - 1)) || ((uintptr_t)d_ws & 7) ||
+        ((uintptr_t)d_out_size & 7))
+        return SPZ_EINVAL;
+    if (dst_cap < sprintz_compress_bound(rows, D, dtype, p)) return SPZ_ENOSPC;
+    if (ws_size < sprintz_workspace_size(rows, D, dtype, p)) return SPZ_ENOSPC;
+    spz::Geom g = make_geom(rows, D, w, p->seg_rows, p->hdr_group, p->learn_shift);
+    g.cap = dst_cap;
+    const bool col = (uint64_t)D * w <= 32;
+    const bool fire = p->forecaster == SPZ_FIRE;
+    uint32_t *ws = (uint32_t *)d_ws;
+    uint8_t *dst = (uint8_t *)d_dst;
+    hipError_t e;
+#define SPZ_ENC(W_, F_, C_) \
+    launch_encode<W_, F_, C_>(d_src, g, ws, dst, d_status, (uint32_t)dtype, p->forecaster, p->learn_shift, d_out_size, stream)
+    if (w == 8) {
+        if (fire) e = col ? SPZ_ENC(8, true, true) : SPZ_ENC(8, true, false);
+        else e = col ? SPZ_ENC(8, false, true) : SPZ_ENC(8, false, false);
+    } else {
+        if (fire) e = col ? SPZ_ENC(16, true, true) : SPZ_ENC(16, true, false);
+        else e = col ? SPZ_ENC(16, false, true) : SPZ_ENC(16, false, false);
+    }
+#undef SPZ_ENC
+    return e == hipSuccess ? SPZ_OK : SPZ_EHIP;
+}
+
+spz_status sprintz_get_info(const void *h_src, size_t n, spz_info *out) {
+    if (!h_src || !out) return SPZ_EINVAL;
+    const uint8_t *s = (const uint8_t *)h_src;
+    if (n < kHeader || memcmp(s, "SPZ1", 4) != 0 || get_le(s + 4, 2) != 1) return SPZ_ECORRUPT;
+    spz_info info;
+    memset(&info, 0, sizeof(info));
+    info.w = s[6];
+    info.dtype = s[7];
+    spz_params_default(&info.params);
+    info.params.forecaster = s[8];
+    info.params.learn_shift = s[9];
+    info.params.hdr_group = s[10];
+    info.params.entropy = s[11];
+    info.D = (uint32_t)get_le(s + 12, 4);
+    info.rows = get_le(s + 16, 8);
+    info.params.seg_rows = (uint32_t)get_le(s + 24, 4);
+    info.nseg = (uint32_t)get_le(s + 28, 4);
+    const uint64_t data_bytes = get_le(s + 32, 8);
+    if (bits_of((spz_dtype)info.dtype) != info.w || info.D == 0) return SPZ_ECORRUPT;
+    if (info.params.forecaster > 1 || info.params.learn_shift > 8 || info.params.entropy != 0) return SPZ_ECORRUPT;
+    if (info.params.seg_rows < 8 || info.params.seg_rows % 8 != 0) return SPZ_ECORRUPT;
+    if (num_segments(info.rows, info.params.seg_rows) != info.nseg) return SPZ_ECORRUPT;
+    info.compressed_size = align16(kHeader + 8ull * (info.nseg + 1)) + data_bytes;
+    info.decompressed_size = info.rows * info.D * (info.w / 8);
+    *out = info;
+    return SPZ_OK;
+}
+
+spz_status sprintz_decompress(const void *d_src, size_t src_size, const spz_info *info, void *d_dst,
+                              size_t dst_cap, int32_t *d_status, hipStream_t stream) {
+    if (!info || !d_src) return SPZ_EINVAL;
+    const uint32_t w = info->w;
+    if (w != 8 && w != 16) return SPZ_EINVAL;
+    if (check_params(&info->params) != SPZ_OK) return SPZ_EINVAL;
+    if (info->D == 0) return SPZ_EINVAL;
+    if (info->D > kMaxD) return SPZ_EUNSUPPORTED;
+    if (info->nseg != num_segments(info->rows, info->params.seg_rows)) return SPZ_EINVAL;
+    if (info->compressed_size > src_size) return SPZ_ENOSPC;
+    if (dst_cap < info->rows * info->D * (w / 8)) return SPZ_ENOSPC;
+    if (info->rows > 0 && !d_dst) return SPZ_EINVAL;
+    if (((uintptr_t)d_src & 15) || ((uintptr_t)d_dst & (w / 8 - 1))) return SPZ_EINVAL;
+    spz::Geom g = make_geom(info->rows, info->D, w, info->params.seg_rows, info->params.hdr_group,
+                            info->params.learn_shift);
+    g.cap = src_size;
+    g.data_bytes = info->compressed_size - g.data_start;
+    const bool col = (uint64_t)info->D * w <= 32;
+    const bool fire = info->params.forecaster == SPZ_FIRE;
+    hipError_t e;
+#define SPZ_DEC(W_, F_, C_) launch_decode<W_, F_, C_>(d_src, g, d_dst, d_status, stream)
+    if (w == 8) {
+        if (fire) e = col ? SPZ_DEC(8, true, true) : SPZ_DEC(8, true, false);
+        else e = col ? SPZ_DEC(8, false, true) : SPZ_DEC(8, false, false);
+    } else {
+        if (fire) e = col ? SPZ_DEC(16, true, true) : SPZ_DEC(16, true, false);
+        else e = col ? SPZ_DEC(16, false, true) : SPZ_DEC(16, false, false);
+    }
+#undef SPZ_DEC
+    return e == hipSuccess ? SPZ_OK : SPZ_EHIP;
+}
+
+const char *sprintz_strerror(spz_status s) {
+    switch (s) {
+        case SPZ_OK: return "ok";
+        case SPZ_EINVAL: return "invalid argument";
+        case SPZ_ENOSPC: return "destination or workspace too small";
+        case SPZ_ECORRUPT: return "corrupt container header";
+        case SPZ_EUNSUPPORTED: return "outside the GPU limits (D <= 64)";
+        case SPZ_EHIP: return "HIP runtime error";
+        case SPZ_ENOMEM: return "out of memory";
+        default: return "unknown status";
+    }
+}
+
+int sprintz_format_version(void) { return 1; }
+
+}  // extern "C"

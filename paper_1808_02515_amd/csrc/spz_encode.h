@@ -1,0 +1,277 @@
+// Sprintz encoder kernels for gfx950.
+//
+// Paper: Algorithm 1 (encodeBlock) applied to every 8-row block of a
+// segment; forecasters of Section 4.2 (delta; FIRE as Algorithm 3 with the
+// practical changes of Section 4.2.2: alpha once per block, one summed
+// gradient update per block from every other sample); zigzag, bit widths,
+// log2(w)-bit headers and column-/row-major payloads of Section 4.3;
+// run-length records for all-zero blocks (Algorithm 1).
+//
+// Two passes over the same per-lane walk: pass 1 (WRITE = false) only sizes
+// every segment; a single-workgroup scan turns the sizes into the offset
+// table; pass 2 (WRITE = true) repeats the walk and writes the bytes.
+#pragma once
+
+#include "spz_device.h"
+
+namespace spz {
+
+// Bytes of the record headers of a segment with nrec records (all groups,
+// each padded to a byte).
+__device__ __forceinline__ uint32_t header_bytes(uint32_t nrec, uint32_t D, uint32_t HB, uint32_t G) {
+    if (G == 0) return (nrec * D * HB + 7) >> 3;
+    uint32_t full = nrec / G, rest = nrec % G;
+    return full * ((G * D * HB + 7) >> 3) + ((rest * D * HB + 7) >> 3);
+}
+
+// Ring of header words per lane group (enough for one record plus a byte).
+__device__ __forceinline__ uint32_t ring_words(uint32_t Dp) { return Dp >= 8 ? Dp / 4 : 2; }
+
+template <int W, bool FIRE, bool COLMAJOR, bool WRITE>
+__global__ __launch_bounds__(kThreads) void k_encode(const typename Elem<W>::T *__restrict__ src, Geom g,
+                                                     uint32_t *__restrict__ seg_info, uint8_t *__restrict__ dst,
+                                                     int32_t *__restrict__ status) {
+    using T = typename Elem<W>::T;
+    constexpr uint32_t HB = W == 8 ? 3 : 4;
+    constexpr uint32_t WB = W / 8;
+    __shared__ uint32_t hring[512];
+    __shared__ uint32_t pbuf[COLMAJOR ? 1 : kThreads * W / 4];
+
+    const uint32_t Dp = 1u << g.dp_log2;
+    const uint32_t gid = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t seg = gid >> g.dp_log2;
+    const uint32_t j = gid & (Dp - 1);
+    if (seg >= g.nseg) return;  // whole lane groups leave together
+    const bool col = j < g.D;
+    const uint32_t D = g.D;
+
+    const uint64_t row0 = (uint64_t)seg * g.S;
+    const uint32_t nr = (uint32_t)min((uint64_t)g.S, g.rows - row0);
+    const uint32_t nblk = nr >> 3, tail = nr & 7u;
+    const T *xs = src + row0 * D + (col ? j : 0);
+
+    // write state
+    const uint32_t gw = threadIdx.x >> g.dp_log2;  // lane group within the workgroup
+    const uint32_t RW = ring_words(Dp);
+    uint32_t *ring = hring + gw * RW;
+    uint32_t *pay = pbuf + (COLMAJOR ? 0 : gw * (Dp * W / 4));
+    uint64_t base = 0;
+    uint32_t nrec_total = 0, seg_size = 0;
+    uint32_t cursor = 4, grp_left = 0, hstart = 0, hbit = 0, hflushed = 0, r = 0;
+    bool overflow = false;
+    auto st = [&](uint64_t pos, uint32_t v) {
+        if (pos < g.cap) dst[pos] = (uint8_t)v;
+        else overflow = true;
+    };
+    if (WRITE) {
+        base = g.data_start + ld_u64_aligned(dst + 64 + 8ull * seg);
+        seg_size = seg_info[2 * seg];
+        nrec_total = seg_info[2 * seg + 1];
+        for (uint32_t k = j; k < RW; k += Dp) ring[k] = 0;
+        if (!COLMAJOR)
+            for (uint32_t k = j; k < Dp * W / 4; k += Dp) pay[k] = 0;
+        if (j == 0) {
+            if (base + 4 <= g.cap) *reinterpret_cast<uint32_t *>(dst + base) = nrec_total;
+            else overflow = true;
+        }
+    }
+
+    uint32_t nrec = 0, payload = 0, run = 0;
+    uint32_t prev = 0;
+    int32_t delta = 0, acc = 0;
+
+    // Emit one record: header code of this lane's column, payload bytes.
+    auto emit = [&](uint32_t code, bool is_rle, uint32_t count, const uint32_t *z, uint32_t width, uint32_t off,
+                    uint32_t wsum) {
+        if (grp_left == 0) {
+            uint32_t cnt = g.G ? min(g.G, nrec_total - r) : nrec_total;
+            hstart = cursor;
+            cursor += (cnt * D * HB + 7) >> 3;
+            hbit = 0;
+            hflushed = 0;
+            grp_left = cnt;
+        }
+        if (code != 0) {
+            uint32_t p = hbit + j * HB;
+            uint32_t w0 = (p >> 5) & (RW - 1), s = p & 31u;
+            atomicOr(&ring[w0], code << s);
+            if (s + HB > 32) atomicOr(&ring[(w0 + 1) & (RW - 1)], code >> (32 - s));
+        }
+        hbit += D * HB;
+        if (is_rle) {
+            if (j == 0) {
+                st(base + cursor, count & 0xFFu);
+                st(base + cursor + 1, count >> 8);
+            }
+            cursor += 2;
+        } else if (COLMAJOR) {
+            // column j: its 8 values, width bits each, LSB first = width bytes
+            uint64_t lo = 0, hi = 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                uint32_t pos = (uint32_t)i * width;
+                if (pos < 64) {
+                    lo |= (uint64_t)z[i] << pos;
+                    if (pos + width > 64) hi |= (uint64_t)z[i] >> (64 - pos);
+                } else {
+                    hi |= (uint64_t)z[i] << (pos - 64);
+                }
+            }
+            for (uint32_t k = 0; k < width; ++k) {
+                uint32_t byte = k < 8 ? (uint32_t)(lo >> (8 * k)) : (uint32_t)(hi >> (8 * (k - 8)));
+                st(base + cursor + off + k, byte & 0xFFu);
+            }
+            cursor += wsum;
+        } else {
+            // row-major: row i = fields of all columns, padded to a byte
+            const uint32_t R = (wsum + 7) >> 3;
+            if (width != 0) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    uint32_t p = (uint32_t)i * 8 * R + off;
+                    uint32_t w0 = p >> 5, s = p & 31u;
+                    atomicOr(&pay[w0], z[i] << s);
+                    if (s + width > 32) atomicOr(&pay[w0 + 1], z[i] >> (32 - s));
+                }
+            }
+            for (uint32_t k = j; k < 8 * R; k += Dp) {
+                uint32_t sh = (k & 3u) * 8;
+                uint32_t old = atomicAnd(&pay[k >> 2], ~(0xFFu << sh));
+                st(base + cursor + k, (old >> sh) & 0xFFu);
+            }
+            cursor += 8 * R;
+        }
+        grp_left--;
+        r++;
+        uint32_t complete = grp_left == 0 ? (hbit + 7) >> 3 : hbit >> 3;
+        for (uint32_t k = hflushed + j; k < complete; k += Dp) {
+            uint32_t wi = (k >> 2) & (RW - 1), sh = (k & 3u) * 8;
+            uint32_t old = atomicAnd(&ring[wi], ~(0xFFu << sh));
+            st(base + hstart + k, (old >> sh) & 0xFFu);
+        }
+        hflushed = complete;
+    };
+
+    for (uint32_t b = 0; b < nblk; ++b) {
+        const int32_t alpha = FIRE ? (acc >> g.sh) : 0;
+        int32_t grad = 0;
+        uint32_t z[8];
+        uint32_t orz = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const uint32_t x = col ? (uint32_t)xs[(uint64_t)(8 * b + i) * D] : 0u;
+            int32_t pred = (int32_t)prev;
+            if (FIRE) pred += (alpha * delta) >> W;
+            const int32_t e = sext<W>((int32_t)x - pred);
+            if (FIRE && (i & 1)) grad += sgn(e) * delta;
+            delta = sext<W>((int32_t)x - (int32_t)prev);
+            prev = x;
+            z[i] = zigzag(e);
+            orz |= z[i];
+        }
+        if (FIRE) acc = min(max(acc + grad, g.acc_lo), g.acc_hi);
+        const uint32_t nbits = bitlen(orz);
+        const uint32_t code = min(nbits, (uint32_t)W - 1);
+        const uint32_t width = code < (uint32_t)W - 1 ? code : (uint32_t)W;
+        const uint32_t incl = group_incl_sum(width, Dp, j);
+        const uint32_t wsum = group_last(incl, Dp);
+        if (wsum == 0) {
+            run++;
+            if (run == kRleMax) {
+                if (WRITE) emit(0, true, run, z, 0, 0, 0);
+                nrec++;
+                payload += 2;
+                run = 0;
+            }
+            continue;
+        }
+        if (run > 0) {
+            if (WRITE) emit(0, true, run, z, 0, 0, 0);
+            nrec++;
+            payload += 2;
+            run = 0;
+        }
+        if (WRITE) emit(code, false, 0, z, width, incl - width, wsum);
+        nrec++;
+        payload += COLMAJOR ? wsum : 8 * ((wsum + 7) >> 3);
+    }
+    if (run > 0) {
+        uint32_t z0[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (WRITE) emit(0, true, run, z0, 0, 0, 0);
+        nrec++;
+        payload += 2;
+    }
+
+    const uint32_t tail_bytes = tail * D * WB;
+    if (!WRITE) {
+        if (j == 0) {
+            uint32_t size = 4 + header_bytes(nrec, D, HB, g.G) + payload + tail_bytes;
+            seg_info[2 * seg] = (size + 15) & ~15u;
+            seg_info[2 * seg + 1] = nrec;
+        }
+        return;
+    }
+    // raw tail rows (last segment only), then zero padding to 16 bytes
+    if (col) {
+        for (uint32_t t = 0; t < tail; ++t) {
+            uint32_t x = (uint32_t)xs[(uint64_t)(8 * nblk + t) * D];
+            uint32_t pos = cursor + (t * D + j) * WB;
+            for (uint32_t q = 0; q < WB; ++q) st(base + pos + q, (x >> (8 * q)) & 0xFFu);
+        }
+    }
+    cursor += tail_bytes;
+    const uint32_t end = (cursor + 15) & ~15u;
+    for (uint32_t k = cursor + j; k < end; k += Dp) st(base + k, 0);
+    if (j == 0 && (end != seg_size || r != nrec_total)) overflow = true;
+    if (overflow && status) atomicOr(status, 2);
+}
+
+// Exclusive scan of the per-segment sizes into the container's offset
+// table, plus the 64-byte container header and *out_size. One workgroup.
+__global__ __launch_bounds__(1024) void k_scan_sizes(const uint32_t *__restrict__ seg_info, Geom g, uint32_t w,
+                                                     uint32_t dtype, uint32_t forecaster, uint32_t learn_shift,
+                                                     uint8_t *__restrict__ dst, uint64_t *__restrict__ out_size,
+                                                     int32_t *__restrict__ status) {
+    __shared__ uint64_t part[1024];
+    const uint32_t t = threadIdx.x;
+    const uint32_t n = g.nseg;
+    const uint32_t per = (n + 1023) / 1024;
+    const uint32_t lo = min(t * per, n), hi = min(lo + per, n);
+    uint64_t s = 0;
+    for (uint32_t k = lo; k < hi; ++k) s += seg_info[2 * k];
+    part[t] = s;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {  // Hillis-Steele inclusive scan
+        uint64_t v = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint64_t off = part[t] - s;
+    uint64_t *tab = reinterpret_cast<uint64_t *>(dst + 64);
+    for (uint32_t k = lo; k < hi; ++k) {
+        tab[k] = off;
+        off += seg_info[2 * k];
+    }
+    const uint64_t total = part[1023];
+    if (t == 0) {
+        tab[n] = total;
+        uint8_t h[64];
+        for (int k = 0; k < 64; ++k) h[k] = 0;
+        h[0] = 'S'; h[1] = 'P'; h[2] = 'Z'; h[3] = '1';
+        h[4] = 1; h[5] = 0;
+        h[6] = (uint8_t)w; h[7] = (uint8_t)dtype; h[8] = (uint8_t)forecaster; h[9] = (uint8_t)learn_shift;
+        h[10] = (uint8_t)g.G; h[11] = 0;
+        for (int k = 0; k < 4; ++k) h[12 + k] = (uint8_t)(g.D >> (8 * k));
+        for (int k = 0; k < 8; ++k) h[16 + k] = (uint8_t)(g.rows >> (8 * k));
+        for (int k = 0; k < 4; ++k) h[24 + k] = (uint8_t)(g.S >> (8 * k));
+        for (int k = 0; k < 4; ++k) h[28 + k] = (uint8_t)(n >> (8 * k));
+        for (int k = 0; k < 8; ++k) h[32 + k] = (uint8_t)(total >> (8 * k));
+        for (int k = 0; k < 64; ++k) dst[k] = h[k];
+        for (uint64_t k = 64 + 8ull * (n + 1); k < g.data_start; ++k) dst[k] = 0;
+        *out_size = g.data_start + total;
+        if (g.data_start + total > g.cap && status) atomicOr(status, 2);
+    }
+}
+
+}  // namespace spz

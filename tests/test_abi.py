@@ -1,0 +1,96 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point that
+include/sprintz.h declares, and its host-only logic (parameters, bounds,
+header parsing, argument validation) behaves. No kernel is launched."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+import paper_1808_02515_amd as spz
+from paper_1808_02515_amd import build as spz_build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(spz.LIB_PATH):
+        spz_build.build()
+    return spz.load()
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "sprintz.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:sprintz|spz)_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_abi():
+    names = _declared_functions()
+    for n in ["sprintz_compress", "sprintz_decompress", "sprintz_get_info", "sprintz_compress_bound",
+              "sprintz_workspace_size", "spz_params_default", "sprintz_strerror", "sprintz_format_version"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for n in _declared_functions():
+        assert hasattr(lib, n), n
+        assert n in spz._SIGNATURES, n
+
+
+def test_params_default(lib):
+    p = spz.spz_params_default()
+    assert p.struct_size == ctypes.sizeof(spz.spz_params)
+    assert (p.forecaster, p.seg_rows, p.hdr_group, p.learn_shift, p.entropy) == (spz.SPZ_FIRE, 1024, 0, 1, 0)
+    assert spz.sprintz_format_version() == 1
+    assert spz.sprintz_strerror(spz.SPZ_ECORRUPT)
+
+
+@pytest.mark.parametrize("dt,code", [(np.int8, 1), (np.uint16, 4)])
+def test_bound_matches_oracle_bound(lib, dt, code):
+    # two separately written bound formulas agree, and real output fits
+    for rows, D, S, G in [(0, 3, 8, 0), (7, 1, 8, 0), (65536, 1, 1024, 0), (100003, 8, 512, 2), (1000, 64, 64, 1)]:
+        p = spz.make_params("fire", S, G)
+        assert spz.sprintz_compress_bound(rows, D, code, p) == oracle.compress_bound(rows, D, dt, S, G)
+        assert spz.sprintz_workspace_size(rows, D, code, p) == 8 * (-(-rows // S)) + 8
+
+
+def test_get_info_parses_oracle_container(lib):
+    x = datagen.ar2_uint16(1000, 5, seed=2)
+    b = oracle.compress(x, "delta", seg_rows=64, hdr_group=2, learn_shift=2)
+    info = spz.sprintz_get_info(b[:64])
+    assert (info.rows, info.D, info.dtype, info.w, info.nseg) == (1000, 5, spz.SPZ_UINT16, 16, 16)
+    assert (info.params.forecaster, info.params.seg_rows, info.params.hdr_group, info.params.learn_shift) == (0, 64, 2, 2)
+    assert info.compressed_size == len(b)
+    assert info.decompressed_size == x.nbytes
+    bad = bytearray(b[:64])
+    bad[0] ^= 1
+    with pytest.raises(spz.SprintzError):
+        spz.sprintz_get_info(bytes(bad))
+    bad = bytearray(b[:64])
+    bad[28] += 1  # segment count inconsistent with rows / seg_rows
+    with pytest.raises(spz.SprintzError):
+        spz.sprintz_get_info(bytes(bad))
+
+
+def test_argument_validation_without_gpu(lib):
+    # every call below is rejected on the host before any HIP call
+    p = spz.make_params("fire", 1024)
+    fake = 1 << 20  # never dereferenced
+    assert spz.sprintz_compress(fake, 100, 0, 4, p, fake, 1 << 20, fake, fake, 1 << 10, 0, 0) == spz.SPZ_EINVAL
+    assert spz.sprintz_compress(fake, 100, 3, 9, p, fake, 1 << 20, fake, fake, 1 << 10, 0, 0) == spz.SPZ_EINVAL
+    assert spz.sprintz_compress(fake, 100, 65, 4, p, fake, 1 << 20, fake, fake, 1 << 10, 0, 0) == spz.SPZ_EUNSUPPORTED
+    assert spz.sprintz_compress(fake, 100, 3, 4, p, fake, 10, fake, fake, 1 << 10, 0, 0) == spz.SPZ_ENOSPC
+    assert spz.sprintz_compress(fake, 100, 3, 4, p, fake, 1 << 20, fake, fake, 0, 0, 0) == spz.SPZ_ENOSPC
+    assert spz.sprintz_compress(fake, 100, 3, 4, p, fake + 8, 1 << 20, fake, fake, 1 << 10, 0, 0) == spz.SPZ_EINVAL
+    for bad in [spz.make_params("fire", 12), spz.make_params("fire", 0), spz.make_params("fire", 1024, 256),
+                spz.make_params("fire", 1024, 0, 9)]:
+        assert spz.sprintz_compress(fake, 100, 3, 4, bad, fake, 1 << 20, fake, fake, 1 << 10, 0, 0) == spz.SPZ_EINVAL
+    info = spz.sprintz_get_info(oracle.compress(np.zeros((16, 2), np.int8), "fire", 8)[:64])
+    assert spz.sprintz_decompress(fake, 10, info, fake, 1 << 20, 0, 0) == spz.SPZ_ENOSPC
+    assert spz.sprintz_decompress(fake, 1 << 20, info, fake, 3, 0, 0) == spz.SPZ_ENOSPC
+    assert spz.sprintz_decompress(fake + 4, 1 << 20, info, fake, 1 << 20, 0, 0) == spz.SPZ_EINVAL
