@@ -10,6 +10,7 @@
 
 #include "sprintz.h"
 #include "spz_decode.h"
+#include "spz_decode_chunked.h"
 #include "spz_encode.h"
 
 namespace {
@@ -82,13 +83,26 @@ hipError_t launch_encode(const void *src, const spz::Geom &g, uint32_t *ws, uint
     return hipGetLastError();
 }
 
+// The chunked decoder needs one header group per segment and 16-byte
+// aligned output rows; any other container goes through the per-lane walker.
+bool chunked_ok(const spz::Geom &g, uint32_t w, const void *dst) {
+    return g.G == 0 && ((uintptr_t)dst & 15) == 0 && ((uint64_t)g.S * g.D * (w / 8)) % 16 == 0;
+}
+
 template <int W, bool FIRE, bool COL>
 hipError_t launch_decode(const void *src, const spz::Geom &g, void *dst, int32_t *status, hipStream_t stream) {
     using T = typename spz::Elem<W>::T;
-    const uint32_t grid = grid_for(g);
-    if (grid > 0)
-        hipLaunchKernelGGL((spz::k_decode<W, FIRE, COL>), dim3(grid), dim3(spz::kThreads), 0, stream,
+    if (g.nseg == 0) return hipGetLastError();
+    if (chunked_ok(g, W, dst)) {
+        const uint32_t spw = 64u >> g.dp_log2;
+        const uint32_t grid = (g.nseg + spw - 1) / spw;
+        const uint64_t magic = ((1ull << 32) + g.D - 1) / g.D;  // ceil(2^32 / D)
+        hipLaunchKernelGGL((spz::k_decode_chunked<W, FIRE, COL>), dim3(grid), dim3(spz::kThreads), 0, stream,
+                           (const uint8_t *)src, g, (T *)dst, magic, status);
+    } else {
+        hipLaunchKernelGGL((spz::k_decode<W, FIRE, COL>), dim3(grid_for(g)), dim3(spz::kThreads), 0, stream,
                            (const uint8_t *)src, g, (T *)dst, status);
+    }
     return hipGetLastError();
 }
 

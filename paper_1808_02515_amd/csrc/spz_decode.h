@@ -117,8 +117,8 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
             const uint32_t z = getbits(p0 + (uint32_t)i * stride, wd);
             const int32_t e = unzigzag(z);
             int32_t s = e;
-            if (FIRE) s += (alpha * delta) >> W;
-            if (FIRE && (i & 1)) grad += sgn(e) * delta;
+            if (FIRE) s += __mul24(alpha, delta) >> W;
+            if (FIRE && (i & 1)) grad += __mul24(sgn(e), delta);
             if (FIRE) delta = sext<W>(s);
             prev = (prev + (uint32_t)s) & MASK;
             vals[i] = (T)prev;

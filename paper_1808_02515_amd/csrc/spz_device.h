@@ -71,4 +71,43 @@ __device__ __forceinline__ uint64_t ld_u64_aligned(const uint8_t *p) {
     return *reinterpret_cast<const uint64_t *>(p);
 }
 
+// Bounded global memory: a buffer resource covers [base, base + bytes) and the
+// hardware returns 0 for reads and drops writes outside it, so a wrong or
+// hostile offset cannot reach other memory. Offsets are 32-bit byte offsets.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kBufferFlags = 0x00020000;  // raw 32-bit buffer, gfx9 family
+
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+};
+
+__device__ __forceinline__ Buf make_buf(const void *base, uint32_t bytes) {
+    Buf b;
+    b.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufferFlags);
+    return b;
+}
+
+__device__ __forceinline__ uint32_t buf_ld32(Buf b, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(b.r, off, 0, 0);
+}
+
+__device__ __forceinline__ void buf_st8(Buf b, uint32_t off, uint32_t v) {
+    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, b.r, off, 0, 0);
+}
+
+__device__ __forceinline__ void buf_st16(Buf b, uint32_t off, uint32_t v) {
+    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)v, b.r, off, 0, 0);
+}
+
+__device__ __forceinline__ void buf_st128(Buf b, uint32_t off, u32x4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(v, b.r, off, 0, 0);
+}
+
+// Make a value the compiler cannot prove uniform usable as a scalar operand.
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+           __builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+
 }  // namespace spz

@@ -161,9 +161,9 @@ __global__ __launch_bounds__(kThreads) void k_encode(const typename Elem<W>::T *
         for (int i = 0; i < 8; ++i) {
             const uint32_t x = col ? (uint32_t)xs[(uint64_t)(8 * b + i) * D] : 0u;
             int32_t pred = (int32_t)prev;
-            if (FIRE) pred += (alpha * delta) >> W;
+            if (FIRE) pred += __mul24(alpha, delta) >> W;
             const int32_t e = sext<W>((int32_t)x - pred);
-            if (FIRE && (i & 1)) grad += sgn(e) * delta;
+            if (FIRE && (i & 1)) grad += __mul24(sgn(e), delta);
             delta = sext<W>((int32_t)x - (int32_t)prev);
             prev = x;
             z[i] = zigzag(e);
