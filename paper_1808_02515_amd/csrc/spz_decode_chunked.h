@@ -4,14 +4,17 @@
 // Paper: Algorithm 2 (decodeBlock). The only step that is inherently serial
 // is the forecaster recurrence of each column (Section 5.3: the serial
 // dependence between decoding one sample and predicting the next is the
-// limit). This kernel therefore moves everything else off the serial path:
+// limit). This kernel moves everything else off the serial path and hides
+// memory latency by staging the next chunk while the current one decodes:
 //
 //   per chunk of up to 16 blocks of every segment of the workgroup
-//   1. parse   (lanes = candidate records): header codes -> widths, column
-//              bit offsets, record sizes; group scans give payload offsets
-//              and the block -> record map; run counts are read here.
-//   2. unpack  (lanes = (segment, block, column)): bit fields -> zigzag
-//              decode -> error e, stored as e * 2^w (FIRE) or e (delta).
+//   1. parse   (lanes = candidate records, from LDS): header codes -> widths,
+//              column bit offsets, record sizes; group scans give payload
+//              offsets and the block -> record map; run counts read here.
+//   2. stage   (all lanes): 16-byte loads of the NEXT chunk's header and
+//              payload windows are issued into registers; they land while
+//      unpack  (lanes = (segment, block, column)) turns this chunk's bit
+//              fields into errors e, stored as e * 2^w (FIRE) or e (delta).
 //   3. serial  (one wavefront, lane = column chain): for FIRE
 //                t = alpha * delta + e * 2^w      (v_mad_i32_i24)
 //                delta = bits [w, 2w) of t, signed (v_bfe_i32)
@@ -20,9 +23,11 @@
 //              delta / 2^w) modulo 2^w; the gradient sign(e) * delta_{i-1}
 //              is summed on odd rows and the accumulator saturates once per
 //              block (practical FIRE, Section 4.2.2).
-//   4. output  (all lanes): samples leave row-major with 16-byte stores.
+//   4. output  (all lanes): samples leave row-major with 16-byte stores; the
+//              staged registers replace the consumed windows in LDS.
 //
 // A workgroup holds 64 chains: 64 / Dp segments of Dp = next_pow2(D) lanes.
+// Every global access goes through a bounded buffer resource.
 #pragma once
 
 #include "spz_device.h"
@@ -33,6 +38,8 @@ constexpr int kChunkBlocks = 16;                 // blocks per chunk per segment
 constexpr int kChunkRows = kChunkBlocks * 8;     // 128
 constexpr int kChainStride = kChunkRows + 4;     // dwords per chain in LDS (bank padding)
 constexpr uint32_t kRleMark = 0xFFu;
+constexpr int kStageUnits = 1120;                // 16-byte units per staging buffer (max over D, w)
+constexpr int kStagePerThread = (kStageUnits + kThreads - 1) / kThreads;
 
 struct SegSlot {
     uint32_t ra;           // segment byte offset relative to the workgroup's first segment
@@ -42,7 +49,31 @@ struct SegSlot {
     uint32_t cursor;       // payload byte position of record r
     uint32_t rle_rem;      // blocks of a run continuing into this chunk
     uint32_t ok;
+    uint32_t hbase;        // staged header window: segment byte offset (16-aligned)
+    uint32_t pbase;        // staged payload window: segment byte offset (16-aligned)
 };
+
+// Staging geometry per segment, in 16-byte units: header window for CB
+// records and payload window for CB records of at most 8*D*(w/8) bytes.
+struct StageGeom {
+    uint32_t hu, pu, nu;
+    uint64_t nu_magic;  // ceil(2^32 / nu)
+};
+
+__host__ __device__ inline StageGeom stage_geom(uint32_t D, uint32_t w, uint32_t CB) {
+    const uint32_t hb = w == 8 ? 3 : 4;
+    StageGeom sg;
+    sg.hu = ((CB * D * hb + 7) / 8 + 47) / 16;
+    sg.pu = (CB * 8 * D * (w / 8) + 31 + 15) / 16;
+    sg.nu = sg.hu + sg.pu;
+    sg.nu_magic = ((1ull << 32) + sg.nu - 1) / sg.nu;
+    return sg;
+}
+
+__host__ __device__ inline uint32_t chunk_blocks(uint32_t dp_log2) {
+    const uint32_t v = 4u << dp_log2;
+    return v < (uint32_t)kChunkBlocks ? v : (uint32_t)kChunkBlocks;
+}
 
 template <int W, bool FIRE, bool COLMAJOR>
 __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__restrict__ src, Geom g,
@@ -53,8 +84,9 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
     constexpr uint32_t CPW = 32 / HB;  // header codes per 32-bit window
 
     __shared__ int32_t E[64 * kChainStride];       // [chain][row]: errors, then samples
+    __shared__ u32x4 STG[kStageUnits];              // staged header + payload windows of one chunk
     __shared__ uint32_t colmeta[64 * kChunkBlocks]; // [segment][record][column]: off | width << 24
-    __shared__ uint32_t recbits[256];               // [segment][record]: payload bit offset
+    __shared__ uint32_t recbits[256];               // [segment][record]: payload bit offset in the window
     __shared__ uint32_t recstride[256];             // [segment][record]: bits per packed row
     __shared__ uint32_t blkrec[256];                // [segment][block]: record index or kRleMark
     __shared__ SegSlot slots[2][64];                // per-segment state, double buffered by chunk
@@ -63,11 +95,12 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
     const uint32_t lg = g.dp_log2;
     const uint32_t Dp = 1u << lg;
     const uint32_t SPW = 64u >> lg;                      // segments per workgroup
-    const uint32_t CB = min((uint32_t)kChunkBlocks, 4u * Dp);
+    const uint32_t CB = chunk_blocks(lg);
     const uint32_t CR = CB * 8;
     const uint32_t D = g.D;
     const uint32_t seg0 = blockIdx.x * SPW;
     const uint32_t nsw = min(SPW, g.nseg - seg0);         // segments of this workgroup
+    const StageGeom sg = stage_geom(D, W, CB);
 
     // bounded views: offset table, this workgroup's container span, its output rows
     const Buf tab = make_buf(src + 64, 8u * (g.nseg + 1));
@@ -82,11 +115,42 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
     const uint64_t wrows = min((uint64_t)nsw * g.S, g.rows - wrow0);
     const Buf out = make_buf(reinterpret_cast<uint8_t *>(dst) + wrow0 * D * WB, (uint32_t)(wrows * D * WB));
 
+    // staging: issue loads of the windows described by slot state st into regs
+    u32x4 reg[kStagePerThread];
+    auto stage_issue = [&](const SegSlot *st) {
+#pragma unroll
+        for (int t = 0; t < kStagePerThread; ++t) {
+            const uint32_t u = tid + (uint32_t)t * kThreads;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (u < nsw * sg.nu) {
+                const uint32_t s = (uint32_t)(((uint64_t)u * sg.nu_magic) >> 32);
+                const uint32_t k = u - s * sg.nu;
+                const SegSlot &sl = st[s];
+                if (sl.ok) {
+                    const uint32_t off = k < sg.hu ? sl.hbase + 16 * k : sl.pbase + 16 * (k - sg.hu);
+                    v = buf_ld128(in, sl.ra + off);
+                }
+            }
+            reg[t] = v;
+        }
+    };
+    auto stage_commit = [&](u32x4 *buf) {
+#pragma unroll
+        for (int t = 0; t < kStagePerThread; ++t) {
+            const uint32_t u = tid + (uint32_t)t * kThreads;
+            if (u < nsw * sg.nu) buf[u] = reg[t];
+        }
+    };
+    auto window_bases = [&](SegSlot &sl) {
+        sl.hbase = (4 + (uint32_t)(((uint64_t)sl.r * D * HB) >> 3)) & ~15u;
+        sl.pbase = sl.cursor & ~15u;
+    };
+
     // ---- per-segment setup ----------------------------------------------
     if (tid < SPW) {
         SegSlot sl;
         sl.ok = 0; sl.nblk = 0; sl.tail = 0; sl.nrec = 0; sl.ext = 0; sl.ra = 0;
-        sl.r = 0; sl.cursor = 0; sl.rle_rem = 0;
+        sl.r = 0; sl.cursor = 0; sl.rle_rem = 0; sl.hbase = 0; sl.pbase = 0;
         if (tid < nsw) {
             const uint32_t seg = seg0 + tid;
             const uint64_t a = tab_ld(seg);
@@ -102,9 +166,13 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
                 sl.ok = sl.nrec <= sl.nblk ? 1u : 0u;
             }
             if (!sl.ok && status) atomicOr(status, 1);
+            window_bases(sl);
         }
         slots[0][tid] = sl;
     }
+    __syncthreads();
+    stage_issue(slots[0]);
+    stage_commit(STG);
     __syncthreads();
 
     // FIRE / delta state of the chain owned by this lane of wave 0
@@ -115,26 +183,34 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
     for (uint32_t c = 0; c < nchunks; ++c) {
         const SegSlot *cur = slots[c & 1];
         SegSlot *nxt = slots[(c + 1) & 1];
+        const uint32_t *stw = reinterpret_cast<const uint32_t *>(STG);
         // ---- 1. parse candidate records --------------------------------
         if (tid < SPW * CB) {
             const uint32_t s = tid / CB, k = tid % CB;
             const SegSlot sl = cur[s];
             const uint32_t nb = sl.ok ? sl.nblk : 0u;
             const uint32_t bic = c * CB < nb ? min(CB, nb - c * CB) : 0u;
-            const uint32_t nwm1 = sl.ok ? (sl.ext >> 2) - 1 : 0u;
-            auto word = [&](uint32_t wi) -> uint32_t { return buf_ld32(in, sl.ra + 4 * min(wi, nwm1)); };
-            auto bits32 = [&](uint32_t p) -> uint32_t {  // 32 bits starting at segment bit p
-                return __builtin_amdgcn_alignbit(word((p >> 5) + 1), word(p >> 5), p & 31u);
+            const uint32_t hw0 = s * sg.nu * 4;                 // first header word of segment s
+            const uint32_t hwl = hw0 + sg.hu * 4 - 2;           // last header word readable as a pair
+            const uint32_t pw0 = hw0 + sg.hu * 4;               // first payload word
+            const uint32_t pwl = pw0 + sg.pu * 4 - 2;
+            auto hbits32 = [&](uint32_t p) -> uint32_t {       // p: bit offset in the header window
+                const uint32_t wi = min(hw0 + (p >> 5), hwl);
+                return __builtin_amdgcn_alignbit(stw[wi + 1], stw[wi], p & 31u);
+            };
+            auto pbits32 = [&](uint32_t p) -> uint32_t {       // p: bit offset in the payload window
+                const uint32_t wi = min(pw0 + (p >> 5), pwl);
+                return __builtin_amdgcn_alignbit(stw[wi + 1], stw[wi], p & 31u);
             };
             const uint32_t rr = sl.r + k;
             const bool cand = bic > 0 && rr < sl.nrec;
             uint32_t total = 0;
             if (cand) {
-                const uint32_t hp = 32 + rr * D * HB;
+                const uint32_t hp = 32 + rr * D * HB - 8 * sl.hbase;
                 uint32_t win = 0;
                 for (uint32_t j = 0; j < D; ++j) {
                     const uint32_t jj = j % CPW;
-                    if (jj == 0) win = bits32(hp + j * HB);
+                    if (jj == 0) win = hbits32(hp + j * HB);
                     const uint32_t code = __builtin_amdgcn_ubfe(win, jj * HB, HB);
                     const uint32_t width = code < (uint32_t)W - 1 ? code : (uint32_t)W;
                     colmeta[(s * CB + k) * Dp + j] = (COLMAJOR ? 8 * total : total) | (width << 24);
@@ -144,16 +220,16 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
             const bool zero = cand && total == 0;
             const uint32_t size = !cand ? 0u : zero ? 2u : (COLMAJOR ? total : 8 * ((total + 7) >> 3));
             const uint32_t incl = group_incl_sum(size, CB, k);
-            const uint32_t off = sl.cursor + incl - size;
+            const uint32_t off = sl.cursor + incl - size;        // segment byte offset of the payload
             uint32_t nblocks = 0;
-            if (cand) nblocks = zero ? (bits32(off * 8) & 0xFFFFu) : 1u;
-            const bool bad_count = cand && nblocks == 0;
+            if (cand) nblocks = zero ? (pbits32(8 * (off - sl.pbase)) & 0xFFFFu) : 1u;
+            const bool bad = cand && (nblocks == 0 || off + size > sl.ext);
             const uint32_t bincl = group_incl_sum(nblocks, CB, k);
             const uint32_t start = sl.rle_rem + bincl - nblocks;
             const uint32_t end = start + nblocks;
             const bool used = cand && start < bic;
             if (used) {
-                recbits[s * CB + k] = off * 8;
+                recbits[s * CB + k] = 8 * (off - sl.pbase);
                 recstride[s * CB + k] = 8 * ((total + 7) >> 3);
                 const uint32_t mark = zero ? kRleMark : k;
                 for (uint32_t q = start; q < min(end, bic); ++q) blkrec[s * CB + q] = mark;
@@ -165,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
             const uint32_t n_used = group_last(nused, CB);
             const uint32_t used_size = group_last(group_incl_sum(used ? size : 0u, CB, k), CB);
             const uint32_t last_end = group_last(group_incl_sum(used && nused == n_used ? end : 0u, CB, k), CB);
-            const uint32_t any_bad = group_last(group_incl_sum(bad_count ? 1u : 0u, CB, k), CB);
+            const uint32_t any_bad = group_last(group_incl_sum(used && bad ? 1u : 0u, CB, k), CB);
             if (k == 0) {
                 SegSlot ns = sl;
                 if (bic > 0) {
@@ -173,22 +249,24 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
                     ns.cursor = sl.cursor + used_size;
                     const uint32_t covered = n_used ? last_end : sl.rle_rem;
                     if (covered < bic || any_bad) {
-                        ns.ok = 0;  // records ran out or a zero run count
+                        ns.ok = 0;  // records ran out, a zero run count, or a payload past the segment
                         if (status) atomicOr(status, 1);
                     }
                     ns.rle_rem = covered >= bic ? covered - bic : 0u;
+                    window_bases(ns);
                 }
                 nxt[s] = ns;
             }
         }
         __syncthreads();
 
-        // ---- 2. unpack: fields -> errors --------------------------------
+        // ---- 2. stage the next chunk; unpack this one --------------------
+        if (c + 1 < nchunks) stage_issue(nxt);
         for (uint32_t it = tid; it < SPW * CB * Dp; it += kThreads) {
             const uint32_t j = it & (Dp - 1);
             const uint32_t q = (it >> lg) % CB;
             const uint32_t s = (it >> lg) / CB;
-            const SegSlot sl = nxt[s];
+            const SegSlot &sl = nxt[s];
             const uint32_t nb = sl.nblk;
             const uint32_t bic = c * CB < nb ? min(CB, nb - c * CB) : 0u;
             if (j >= D || q >= bic) continue;
@@ -199,7 +277,8 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
 #pragma unroll
                 for (int i = 0; i < 8; ++i) v[i] = 0;
             } else {
-                const uint32_t nwm1 = (sl.ext >> 2) - 1;
+                const uint32_t pw0 = s * sg.nu * 4 + sg.hu * 4;
+                const uint32_t pwl = pw0 + sg.pu * 4 - 2;
                 const uint32_t cm = colmeta[(s * CB + k) * Dp + j];
                 const uint32_t width = cm >> 24;
                 const uint32_t p0 = recbits[s * CB + k] + (cm & 0xFFFFFFu);
@@ -207,10 +286,9 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const uint32_t p = p0 + (uint32_t)i * stride;
-                    const uint32_t wi = p >> 5;
-                    const uint32_t lo = buf_ld32(in, sl.ra + 4 * min(wi, nwm1));
-                    const uint32_t hi = buf_ld32(in, sl.ra + 4 * min(wi + 1, nwm1));
-                    const uint32_t z = __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(hi, lo, p & 31u), 0u, width);
+                    const uint32_t wi = min(pw0 + (p >> 5), pwl);
+                    const uint32_t z =
+                        __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(stw[wi + 1], stw[wi], p & 31u), 0u, width);
                     const int32_t er = unzigzag(z);
                     v[i] = FIRE ? (int32_t)((uint32_t)er << W) : er;
                 }
@@ -223,8 +301,7 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
         // ---- 3. serial recurrence (wave 0) ------------------------------
         if (tid < 64) {
             const uint32_t s = tid >> lg, j = tid & (Dp - 1);
-            const SegSlot sl = nxt[s];
-            const uint32_t nb = sl.nblk;
+            const uint32_t nb = nxt[s].nblk;
             const uint32_t bic = c * CB < nb ? min(CB, nb - c * CB) : 0u;
             if (j < D) {
                 int32_t *e = &E[tid * kChainStride];
@@ -260,12 +337,11 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
         }
         __syncthreads();
 
-        // ---- 4. output: row-major, 16-byte units ------------------------
+        // ---- 4. output: row-major, 16-byte units; commit the staging ----
         {
             constexpr uint32_t VPU = 16 / WB;  // values per 16-byte unit
             for (uint32_t s = 0; s < SPW; ++s) {
-                const SegSlot sl = nxt[s];
-                const uint32_t nb = sl.nblk;
+                const uint32_t nb = nxt[s].nblk;
                 const uint32_t bic = c * CB < nb ? min(CB, nb - c * CB) : 0u;
                 if (bic == 0) continue;
                 const uint32_t nvals = bic * 8 * D;
@@ -295,6 +371,8 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
                 }
             }
         }
+        // this chunk's windows were last read by the unpack: reuse the buffer
+        if (c + 1 < nchunks) stage_commit(STG);
         __syncthreads();
     }
 

@@ -91,6 +91,10 @@ __device__ __forceinline__ uint32_t buf_ld32(Buf b, uint32_t off) {
     return __builtin_amdgcn_raw_buffer_load_b32(b.r, off, 0, 0);
 }
 
+__device__ __forceinline__ u32x4 buf_ld128(Buf b, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(b.r, off, 0, 0);
+}
+
 __device__ __forceinline__ void buf_st8(Buf b, uint32_t off, uint32_t v) {
     __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, b.r, off, 0, 0);
 }
