@@ -40,6 +40,7 @@ constexpr int kChainStride = kChunkRows + 4;     // dwords per chain in LDS (ban
 constexpr uint32_t kRleMark = 0xFFu;
 constexpr int kStageUnits = 1120;                // 16-byte units per staging buffer (max over D, w)
 constexpr int kStagePerThread = (kStageUnits + kThreads - 1) / kThreads;
+constexpr int kUnpackPerThread = 64 * kChunkBlocks / kThreads;  // (segment, block, column) items
 
 struct SegSlot {
     uint32_t ra;           // segment byte offset relative to the workgroup's first segment
@@ -101,6 +102,13 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
     const uint32_t seg0 = blockIdx.x * SPW;
     const uint32_t nsw = min(SPW, g.nseg - seg0);         // segments of this workgroup
     const StageGeom sg = stage_geom(D, W, CB);
+    // blocks of segment s (of this workgroup) in chunk c, from the geometry alone
+    auto blocks_in_chunk = [&](uint32_t s, uint32_t c) -> uint32_t {
+        const uint32_t nb = (uint32_t)min((uint64_t)g.S, g.rows - (uint64_t)(seg0 + s) * g.S) >> 3;
+        return c * CB < nb ? min(CB, nb - c * CB) : 0u;
+    };
+    const uint32_t ups0 = (CR * D * WB + 15) / 16;
+    const uint64_t ups_magic = ((1ull << 32) + ups0 - 1) / ups0;
 
     // bounded views: offset table, this workgroup's container span, its output rows
     const Buf tab = make_buf(src + 64, 8u * (g.nseg + 1));
@@ -262,18 +270,17 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
 
         // ---- 2. stage the next chunk; unpack this one --------------------
         if (c + 1 < nchunks) stage_issue(nxt);
-        for (uint32_t it = tid; it < SPW * CB * Dp; it += kThreads) {
+#pragma unroll
+        for (int ti = 0; ti < kUnpackPerThread; ++ti) {
+            const uint32_t it = tid + (uint32_t)ti * kThreads;
             const uint32_t j = it & (Dp - 1);
             const uint32_t q = (it >> lg) % CB;
             const uint32_t s = (it >> lg) / CB;
-            const SegSlot &sl = nxt[s];
-            const uint32_t nb = sl.nblk;
-            const uint32_t bic = c * CB < nb ? min(CB, nb - c * CB) : 0u;
-            if (j >= D || q >= bic) continue;
+            if (s >= nsw || j >= D || q >= blocks_in_chunk(s, c)) continue;
             int32_t *e = &E[(s * Dp + j) * kChainStride + q * 8];
             const uint32_t k = blkrec[s * CB + q];
             int32_t v[8];
-            if (k >= CB || !sl.ok) {
+            if (k >= CB || !nxt[s].ok) {
 #pragma unroll
                 for (int i = 0; i < 8; ++i) v[i] = 0;
             } else {
@@ -301,8 +308,7 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
         // ---- 3. serial recurrence (wave 0) ------------------------------
         if (tid < 64) {
             const uint32_t s = tid >> lg, j = tid & (Dp - 1);
-            const uint32_t nb = nxt[s].nblk;
-            const uint32_t bic = c * CB < nb ? min(CB, nb - c * CB) : 0u;
+            const uint32_t bic = s < nsw ? blocks_in_chunk(s, c) : 0u;
             if (j < D) {
                 int32_t *e = &E[tid * kChainStride];
                 for (uint32_t q = 0; q < bic; ++q) {
@@ -317,7 +323,7 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
                             // low 32 bits of alpha * delta + e * 2^w (both factors fit 24 bits)
                             const int32_t tt = (int32_t)((uint32_t)__mul24(alpha, delta) + (uint32_t)v[i]);
                             const int32_t dn = __builtin_amdgcn_sbfe(tt, (uint32_t)W, (uint32_t)W);
-                            if (i & 1) grad += __mul24(sgn(v[i]), delta);
+                            if (i & 1) grad += __mul24(sgn_med3(v[i]), delta);
                             delta = dn;
                             xprev += (uint32_t)dn;
                             v[i] = (int32_t)xprev;
@@ -339,34 +345,34 @@ __global__ __launch_bounds__(kThreads) void k_decode_chunked(const uint8_t *__re
 
         // ---- 4. output: row-major, 16-byte units; commit the staging ----
         {
-            constexpr uint32_t VPU = 16 / WB;  // values per 16-byte unit
-            for (uint32_t s = 0; s < SPW; ++s) {
-                const uint32_t nb = nxt[s].nblk;
-                const uint32_t bic = c * CB < nb ? min(CB, nb - c * CB) : 0u;
-                if (bic == 0) continue;
-                const uint32_t nvals = bic * 8 * D;
-                const uint32_t nunits = (nvals + VPU - 1) / VPU;
+            constexpr uint32_t VPU = 16 / WB;             // values per 16-byte unit
+            const uint32_t ups = (CR * D * WB + 15) / 16;  // units per full chunk of one segment
+            for (uint32_t u = tid; u < nsw * ups; u += kThreads) {
+                const uint32_t s = (uint32_t)(((uint64_t)u * ups_magic) >> 32);  // u / ups
+                const uint32_t f0 = (u - s * ups) * VPU;
+                const uint32_t nvals = blocks_in_chunk(s, c) * 8 * D;
+                if (f0 >= nvals) continue;
+                uint32_t row = (uint32_t)(((uint64_t)f0 * div_magic) >> 32);  // f0 / D
+                uint32_t j = f0 - row * D;
+                uint32_t w4[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (uint32_t t = 0; t < VPU; ++t) {
+                    // rows past the chunk read padding of the same chain: harmless, never stored
+                    const uint32_t x = (uint32_t)E[(s * Dp + j) * kChainStride + min(row, (uint32_t)kChunkRows - 1)];
+                    w4[t / (4 / WB)] |= (x & ((1u << W) - 1)) << (W * (t % (4 / WB)));
+                    const bool wrap = ++j == D;
+                    j = wrap ? 0u : j;
+                    row += wrap ? 1u : 0u;
+                }
                 const uint32_t obase = (s * g.S + c * CR) * D * WB;  // byte offset in the workgroup's rows
-                for (uint32_t u = tid; u < nunits; u += kThreads) {
-                    const uint32_t f0 = u * VPU;
-                    uint32_t row = (uint32_t)(((uint64_t)f0 * div_magic) >> 32);  // f0 / D
-                    uint32_t j = f0 - row * D;
-                    uint32_t w4[4] = {0, 0, 0, 0};
-                    const uint32_t n = min(VPU, nvals - f0);
-                    for (uint32_t t = 0; t < n; ++t) {
-                        const uint32_t x = (uint32_t)E[(s * Dp + j) * kChainStride + row] & ((1u << W) - 1);
-                        w4[t / (4 / WB)] |= x << (W * (t % (4 / WB)));
-                        if (++j == D) { j = 0; ++row; }
-                    }
-                    if (n == VPU) {
-                        u32x4 v4 = {w4[0], w4[1], w4[2], w4[3]};
-                        buf_st128(out, obase + f0 * WB, v4);
-                    } else {
-                        for (uint32_t t = 0; t < n; ++t) {
-                            const uint32_t x = w4[t / (4 / WB)] >> (W * (t % (4 / WB)));
-                            if (WB == 1) buf_st8(out, obase + (f0 + t), x);
-                            else buf_st16(out, obase + (f0 + t) * 2, x);
-                        }
+                if (f0 + VPU <= nvals) {
+                    u32x4 v4 = {w4[0], w4[1], w4[2], w4[3]};
+                    buf_st128(out, obase + f0 * WB, v4);
+                } else {
+                    for (uint32_t t = 0; t < nvals - f0; ++t) {
+                        const uint32_t x = w4[t / (4 / WB)] >> (W * (t % (4 / WB)));
+                        if (WB == 1) buf_st8(out, obase + (f0 + t), x);
+                        else buf_st16(out, obase + (f0 + t) * 2, x);
                     }
                 }
             }

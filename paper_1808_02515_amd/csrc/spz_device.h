@@ -51,6 +51,14 @@ __device__ __forceinline__ int32_t unzigzag(uint32_t z) {
 
 __device__ __forceinline__ int32_t sgn(int32_t e) { return min(max(e, -1), 1); }
 
+// sign(e) in one v_med3_i32 (the compiler lowers the clamp above to two
+// compare/select pairs).
+__device__ __forceinline__ int32_t sgn_med3(int32_t e) {
+    int32_t r;
+    asm("v_med3_i32 %0, %1, -1, 1" : "=v"(r) : "v"(e));
+    return r;
+}
+
 // Number of significant bits (0 for 0).
 __device__ __forceinline__ uint32_t bitlen(uint32_t v) { return 32u - (uint32_t)__clz((int)v); }
 
