@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--seg-rows", type=int, default=1024)
     ap.add_argument("--rotate", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run plain device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the codec has no multi-GPU path in this build "
@@ -91,6 +93,17 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(7)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(max(args.steps, 1)):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n, "copies": max(args.steps, 1)}), flush=True)
+        return
 
     import datagen
     import paper_1808_02515_amd as spz
