@@ -12,6 +12,7 @@
 #include "spz_decode.h"
 #include "spz_decode_chunked.h"
 #include "spz_encode.h"
+#include "spz_encode_chunked.h"
 
 namespace {
 
@@ -66,11 +67,35 @@ uint32_t grid_for(const spz::Geom &g) {
     return (uint32_t)((lanes + spz::kThreads - 1) / spz::kThreads);
 }
 
+// The chunked encoder needs one header group per segment, 16-byte aligned
+// segment rows in a 16-byte aligned input, and the workgroup's whole-segment
+// header arrays and chunk payloads inside its LDS staging buffers; anything
+// else goes through the per-lane walker.
+bool enc_chunked_ok(const spz::Geom &g, uint32_t w, const void *src) {
+    if (g.G != 0 || ((uintptr_t)src & 15) || ((uint64_t)g.S * g.D * (w / 8)) % 16 != 0) return false;
+    const uint32_t spw = 64u >> g.dp_log2;
+    const uint32_t cb = spz::enc_chunk_blocks(g.dp_log2);
+    const uint64_t hdr_seg = (spz::enc_hdr_cap(g.S >> 3, g.D, w) + 15) & ~15ull;
+    const uint64_t out_seg = ((uint64_t)cb * 8 * g.D * (w / 8) + 6 * cb + 15) & ~15ull;
+    return spw * hdr_seg <= (uint64_t)spz::kEncHdrBytes && spw * out_seg <= 4ull * spz::kEncOutWords;
+}
+
 template <int W, bool FIRE, bool COL>
 hipError_t launch_encode(const void *src, const spz::Geom &g, uint32_t *ws, uint8_t *dst, int32_t *status,
                          uint32_t dtype, uint32_t forecaster, uint32_t learn_shift, uint64_t *out_size,
                          hipStream_t stream) {
     using T = typename spz::Elem<W>::T;
+    if (g.nseg > 0 && enc_chunked_ok(g, W, src)) {
+        const uint32_t spw = 64u >> g.dp_log2;
+        const uint32_t grid = (g.nseg + spw - 1) / spw;
+        hipLaunchKernelGGL((spz::k_encode_chunked<W, FIRE, COL, false>), dim3(grid), dim3(spz::kThreads), 0,
+                           stream, (const uint8_t *)src, g, ws, dst, status);
+        hipLaunchKernelGGL(spz::k_scan_sizes, dim3(1), dim3(1024), 0, stream, ws, g, (uint32_t)W, dtype,
+                           forecaster, learn_shift, dst, out_size, status);
+        hipLaunchKernelGGL((spz::k_encode_chunked<W, FIRE, COL, true>), dim3(grid), dim3(spz::kThreads), 0,
+                           stream, (const uint8_t *)src, g, ws, dst, status);
+        return hipGetLastError();
+    }
     const uint32_t grid = grid_for(g);
     if (grid > 0)
         hipLaunchKernelGGL((spz::k_encode<W, FIRE, COL, false>), dim3(grid), dim3(spz::kThreads), 0, stream,

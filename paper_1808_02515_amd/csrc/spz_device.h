@@ -99,6 +99,10 @@ __device__ __forceinline__ uint32_t buf_ld32(Buf b, uint32_t off) {
     return __builtin_amdgcn_raw_buffer_load_b32(b.r, off, 0, 0);
 }
 
+__device__ __forceinline__ uint32_t buf_ld8(Buf b, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b8(b.r, off, 0, 0);
+}
+
 __device__ __forceinline__ u32x4 buf_ld128(Buf b, uint32_t off) {
     return __builtin_amdgcn_raw_buffer_load_b128(b.r, off, 0, 0);
 }
