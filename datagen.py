@@ -2,7 +2,7 @@
 
 This module holds no codec arithmetic: it only draws the integer time series
 that both the CPU oracle and the GPU library are fed. The paper's own speed
-experiments use synthetic data too (Section 5.3: uniform random values at
+experiments use synthetic data too (Section 5.4: uniform random values at
 full range); the shaped generators below mimic sensor streams -- random
 walks, stationary AR(2) columns and constant runs -- because the datasets of
 the paper's ratio experiments (UCR, PAMAP, MSRC-12, UCI Gas, AMPDs) are not

@@ -3,7 +3,7 @@
  *
  * Sprintz (Blalock, Madden & Guttag, IMWUT 2018) compresses a multivariate
  * integer time series: T samples (rows) of D columns, every element an
- * integer of bitwidth w = 8 or 16 stored row-major (Section 3.1,
+ * integer of bitwidth w = 8 or 16 stored row-major (Section 2.1,
  * Definitions). Per column a forecaster predicts each sample (delta coding,
  * Section 4.2.1, or FIRE, Section 4.2.2 / Algorithm 3); the errors are
  * zigzag coded, every block of 8 rows gets one bit width per column, the

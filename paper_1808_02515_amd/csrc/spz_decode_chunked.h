@@ -2,7 +2,7 @@
 // segment).
 //
 // Paper: Algorithm 2 (decodeBlock). The only step that is inherently serial
-// is the forecaster recurrence of each column (Section 5.3: the serial
+// is the forecaster recurrence of each column (Section 5.4: the serial
 // dependence between decoding one sample and predicting the next is the
 // limit). This kernel moves everything else off the serial path and hides
 // memory latency by staging the next chunk while the current one decodes:

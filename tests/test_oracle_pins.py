@@ -101,7 +101,7 @@ def test_delta_residuals_closed_form(dt):
 
 
 def test_paper_isolated_spike_example():
-    # Section 5.6: {0, -1, 0, 0} delta-codes to {0, -1, 1, 0}; zigzag
+    # Section 5.7: {0, -1, 0, 0} delta-codes to {0, -1, 1, 0}; zigzag
     # {0, 1, 2, 0} needs 2 bits where the raw zigzag {0, 1, 0, 0} needs 1.
     x = np.array([0, -1, 0, 0, 0, 0, 0, 0], dtype=np.int8)
     e, _ = oracle.residuals(x, "delta")
