@@ -11,6 +11,7 @@
 #include "sprintz.h"
 #include "spz_decode.h"
 #include "spz_decode_chunked.h"
+#include "spz_decode_pc.h"
 #include "spz_encode.h"
 #include "spz_encode_chunked.h"
 
@@ -108,8 +109,9 @@ hipError_t launch_encode(const void *src, const spz::Geom &g, uint32_t *ws, uint
     return hipGetLastError();
 }
 
-// The chunked decoder needs one header group per segment and 16-byte
-// aligned output rows; any other container goes through the per-lane walker.
+// The chunked decoders need one header group per segment and 16-byte
+// aligned output rows; D = 1, 2, 4, 8, 16 take the producer/consumer kernel,
+// other D the phase-split one, and any other container the per-lane walker.
 bool chunked_ok(const spz::Geom &g, uint32_t w, const void *dst) {
     return g.G == 0 && ((uintptr_t)dst & 15) == 0 && ((uint64_t)g.S * g.D * (w / 8)) % 16 == 0;
 }
@@ -118,7 +120,20 @@ template <int W, bool FIRE, bool COL>
 hipError_t launch_decode(const void *src, const spz::Geom &g, void *dst, int32_t *status, hipStream_t stream) {
     using T = typename spz::Elem<W>::T;
     if (g.nseg == 0) return hipGetLastError();
-    if (chunked_ok(g, W, dst)) {
+    if (chunked_ok(g, W, dst) && (g.D & (g.D - 1)) == 0 && g.D <= 16) {
+        const uint32_t spw = 64u / g.D;
+        const uint32_t grid = (g.nseg + spw - 1) / spw;
+        switch (g.D) {
+#define SPZ_PC(D_)                                                                                        \
+    case D_:                                                                                              \
+        hipLaunchKernelGGL((spz::k_decode_pc<W, FIRE, D_, spz::kPcProducers>), dim3(grid),                \
+                           dim3(64 * (spz::kPcProducers + 1)), 0, stream, (const uint8_t *)src, g, (T *)dst, \
+                           status);                                                                       \
+        break;
+            SPZ_PC(1) SPZ_PC(2) SPZ_PC(4) SPZ_PC(8) SPZ_PC(16)
+#undef SPZ_PC
+        }
+    } else if (chunked_ok(g, W, dst)) {
         const uint32_t spw = 64u >> g.dp_log2;
         const uint32_t grid = (g.nseg + spw - 1) / spw;
         const uint64_t magic = ((1ull << 32) + g.D - 1) / g.D;  // ceil(2^32 / D)

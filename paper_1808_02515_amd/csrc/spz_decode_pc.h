@@ -1,0 +1,403 @@
+// Producer/consumer Sprintz decoder for gfx950 (header group = whole
+// segment, D a power of two up to 16).
+//
+// Paper: Algorithm 2 (decodeBlock) with the forecasters of Section 4.2. Of
+// the decoding work only the forecaster recurrence is serial (Section 5.4
+// names the dependence of each prediction on the previous sample as the
+// limit). A workgroup therefore splits into NP producer wavefronts and one
+// consumer wavefront that work on consecutive chunks at the same time:
+//
+//   producers (chunk t)   parse   lanes = (segment, candidate record k of the
+//                                 chunk): the record's header codes give its
+//                                 width sum and byte size; scans over k give
+//                                 payload offsets, run counts and the blocks
+//                                 each record covers
+//                         stage   16-byte loads of chunk t+1's header and
+//                                 payload windows into registers
+//                         unpack  lanes = (segment, block, column): 8 fields
+//                                 each, aligned two-dword LDS reads and a
+//                                 funnel shift; unzigzag; the errors e go to
+//                                 an LDS buffer per column chain
+//   consumer (chunk t-1)  lane = column chain. For FIRE
+//                              t     = e * 2^w + alpha * delta   (v_mad_i32_i24)
+//                              delta = bits [w, 2w) of t, signed   (v_bfe_i32)
+//                              x    += delta
+//                         which equals x_hat + e with x_hat = x_{i-1} +
+//                         floor(alpha * delta / 2^w) modulo 2^w; sgn(e) *
+//                         delta_{i-1} is summed on odd rows and the
+//                         accumulator saturates once per block (practical
+//                         FIRE, Section 4.2.2). Samples go to an LDS image of
+//                         the chunk's rows, which leaves with 16-byte stores.
+//
+// A block inside a run of zero blocks decodes as a block whose errors are
+// all 0 (reading R9: the prediction alone; sgn(0) = 0 leaves the FIRE
+// accumulator as it is), so runs need no separate path. One barrier per chunk
+// hands the error buffers over (double buffered). Every global access goes
+// through a bounded buffer resource; every LDS access is aligned.
+#pragma once
+
+#include "spz_device.h"
+
+namespace spz {
+
+constexpr int kPcChunkBlocks = 8;
+constexpr int kPcProducers = 2;      // producer wavefronts per workgroup
+constexpr uint32_t kPcZero = 0xFFu;  // block map entry of a zero (run) block
+
+template <int CTRL> __device__ __forceinline__ uint32_t pc_dpp(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
+}
+
+// Inclusive sum over an aligned group of N <= 16 lanes (one DPP row).
+template <int N> __device__ __forceinline__ uint32_t pc_incl(uint32_t v, uint32_t i) {
+    if constexpr (N >= 2) { const uint32_t t = pc_dpp<0x111>(v); v += i >= 1 ? t : 0u; }
+    if constexpr (N >= 4) { const uint32_t t = pc_dpp<0x112>(v); v += i >= 2 ? t : 0u; }
+    if constexpr (N >= 8) { const uint32_t t = pc_dpp<0x114>(v); v += i >= 4 ? t : 0u; }
+    if constexpr (N >= 16) { const uint32_t t = pc_dpp<0x118>(v); v += i >= 8 ? t : 0u; }
+    return v;
+}
+
+// Sum over an aligned group of N <= 16 lanes, in every lane of the group.
+template <int N> __device__ __forceinline__ uint32_t pc_total(uint32_t v) {
+    if constexpr (N >= 2) v += pc_dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+    if constexpr (N >= 4) v += pc_dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+    if constexpr (N >= 8) v += pc_dpp<0x141>(v);  // row_half_mirror
+    if constexpr (N >= 16) v += pc_dpp<0x140>(v); // row_mirror
+    return v;
+}
+
+// The 32 bits starting at bit p of an LDS word array (two aligned reads).
+__device__ __forceinline__ uint32_t lds_bits32(const uint32_t *w, uint32_t p) {
+    const uint32_t *q = w + (p >> 5);
+    return __builtin_amdgcn_alignbit(q[1], q[0], p);
+}
+
+struct PcSeg {
+    uint32_t ra, ext, nrec, nblk;   // container span (relative to the workgroup's), records, blocks
+    uint32_t r, cursor, rle_rem;    // next record, its payload byte, run blocks pending
+    uint32_t hbase, pbase;          // staged windows (segment byte offsets, 16-aligned)
+    uint32_t ok, tail, pad;
+};
+
+template <int W, int D, int CB, int NP> struct PcGeom {
+    static constexpr uint32_t HB = W == 8 ? 3 : 4;
+    static constexpr uint32_t WB = W / 8;
+    static constexpr uint32_t SPW = 64 / D;                        // segments per workgroup
+    static constexpr uint32_t SPP = SPW / NP;                      // segments per producer wave
+    static constexpr uint32_t MAXREC = 8 * D * WB;                 // largest record payload
+    static constexpr uint32_t HU = (CB * D * HB / 8 + 28 + 15) / 16;   // header window units
+    static constexpr uint32_t PU = (CB * MAXREC + 24 + 15) / 16;       // payload window units
+    static constexpr uint32_t NU = HU + PU;
+    static constexpr uint32_t PAIRS = SPP * CB;                    // (segment, candidate) per producer
+    static constexpr uint32_t PPASS = (PAIRS + 63) / 64;           // parse passes
+    static constexpr uint32_t SUNITS = SPP * NU;                   // staged units per producer
+    static constexpr uint32_t SPASS = (SUNITS + 63) / 64;
+    static constexpr uint32_t ITEMS = SPP * CB * D;                // unpack items per producer
+    static constexpr uint32_t IPASS = (ITEMS + 63) / 64;
+    static constexpr uint32_t ZSTR = CB * 8 * WB + 16;             // error buffer bytes per chain
+    static constexpr bool WIDE = D * WB >= 16;
+    static constexpr uint32_t OSEG = CB * 8 * D * WB + (WIDE ? D * WB : 4);  // row image stride
+    static constexpr uint32_t UPL = CB * 8 * WB / 16;              // 16-byte output units per lane
+};
+
+template <int W, bool FIRE, int D, int NP>
+__global__ __launch_bounds__(64 * (NP + 1)) void k_decode_pc(const uint8_t *__restrict__ src, Geom g,
+                                                            typename Elem<W>::T *__restrict__ dst,
+                                                            int32_t *__restrict__ status) {
+    constexpr int CB = kPcChunkBlocks;
+    using G = PcGeom<W, D, CB, NP>;
+    constexpr uint32_t HB = G::HB, WB = G::WB, SPW = G::SPW, SPP = G::SPP, HU = G::HU, NU = G::NU;
+    constexpr uint32_t ZSTR = G::ZSTR, OSEG = G::OSEG;
+    constexpr bool ROW = D * W > 32;   // row-major payloads (reading R13)
+    static_assert(SPP * NP == SPW && CB <= 16, "geometry");
+
+    __shared__ u32x4 STG[SPW * NU];                   // [segment][header window | payload window]
+    __shared__ u32x4 ZB4[2 * 64 * ZSTR / 16];          // [buffer][chain] errors of a chunk
+    __shared__ uint32_t OUTW[SPW * OSEG / 4];         // [segment] output rows of a chunk
+    __shared__ u32x4 REC[SPW * CB];                   // [segment][candidate]: codes lo, hi, payload bit, bits per row
+    __shared__ uint32_t BM[SPW * CB];                 // [segment][block]: candidate or kPcZero
+    __shared__ PcSeg SEG[SPW];
+    const uint32_t *const stgw = reinterpret_cast<const uint32_t *>(STG);
+    uint8_t *const zb = reinterpret_cast<uint8_t *>(ZB4);
+    uint8_t *const outb = reinterpret_cast<uint8_t *>(OUTW);
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t wave = tid >> 6, lane = tid & 63;
+    const bool consumer = wave == NP;
+    const uint32_t seg0 = blockIdx.x * SPW;
+    const uint32_t nsw = min(SPW, g.nseg - seg0);
+
+    // bounded views: offset table, this workgroup's container span, its output rows
+    const Buf tab = make_buf(src + 64, 8u * (g.nseg + 1));
+    auto tab_ld = [&](uint32_t k) -> uint64_t {
+        return (uint64_t)buf_ld32(tab, 8 * k) | ((uint64_t)buf_ld32(tab, 8 * k + 4) << 32);
+    };
+    const uint64_t a_wg = uniform64(tab_ld(seg0));
+    const uint64_t b_wg = uniform64(tab_ld(seg0 + nsw));
+    const bool wg_ok = a_wg <= b_wg && b_wg <= g.data_bytes && b_wg - a_wg <= 0x7FFFFFF0ull;
+    const Buf in = make_buf(src + g.data_start + (wg_ok ? a_wg : 0), wg_ok ? (uint32_t)(b_wg - a_wg) : 0u);
+    const uint64_t wrow0 = (uint64_t)seg0 * g.S;
+    const uint64_t wrows = min((uint64_t)nsw * g.S, g.rows - wrow0);
+    const Buf out = make_buf(reinterpret_cast<uint8_t *>(dst) + wrow0 * D * WB, (uint32_t)(wrows * D * WB));
+    auto seg_blocks = [&](uint32_t s) -> uint32_t {
+        return s < nsw ? (uint32_t)min((uint64_t)g.S, g.rows - (uint64_t)(seg0 + s) * g.S) >> 3 : 0u;
+    };
+    const uint32_t nchunks = ((g.S >> 3) + CB - 1) / CB;
+    uint32_t bad = 0;
+
+    // ---- producer: segment setup and the first chunk's windows ---------------
+    const uint32_t ps0 = wave * SPP;   // this producer's first segment
+    u32x4 reg[G::SPASS];
+    auto stage_issue = [&]() {
+#pragma unroll
+        for (uint32_t t = 0; t < G::SPASS; ++t) {
+            const uint32_t u = lane + 64 * t;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (u < G::SUNITS) {
+                const uint32_t s = ps0 + u / NU, k = u % NU;
+                const PcSeg &sg = SEG[s];
+                if (sg.ok) v = buf_ld128(in, sg.ra + (k < HU ? sg.hbase + 16 * k : sg.pbase + 16 * (k - HU)));
+            }
+            reg[t] = v;
+        }
+    };
+    auto stage_commit = [&]() {
+#pragma unroll
+        for (uint32_t t = 0; t < G::SPASS; ++t) {
+            const uint32_t u = lane + 64 * t;
+            if (u < G::SUNITS) STG[ps0 * NU + u] = reg[t];
+        }
+    };
+    if (!consumer) {
+        if (lane < SPP) {
+            const uint32_t s = ps0 + lane;
+            PcSeg sg;
+            sg.ra = 0; sg.ext = 0; sg.nrec = 0; sg.nblk = 0; sg.r = 0; sg.cursor = 4; sg.rle_rem = 0;
+            sg.ok = 0; sg.tail = 0; sg.pad = 0;
+            if (s < nsw) {
+                const uint32_t seg = seg0 + s;
+                const uint64_t a = tab_ld(seg), b = tab_ld(seg + 1);
+                const uint32_t nr = (uint32_t)min((uint64_t)g.S, g.rows - (uint64_t)seg * g.S);
+                sg.tail = nr & 7u;
+                if (wg_ok && a_wg <= a && a <= b && b <= b_wg && !((a | b) & 15u) && b - a >= 16) {
+                    sg.ra = (uint32_t)(a - a_wg);
+                    sg.ext = (uint32_t)(b - a);
+                    sg.nrec = buf_ld32(in, sg.ra);
+                    sg.ok = sg.nrec <= (nr >> 3) ? 1u : 0u;
+                }
+                if (sg.ok) {
+                    sg.nblk = nr >> 3;
+                    sg.cursor = 4 + (uint32_t)(((uint64_t)sg.nrec * D * HB + 7) >> 3);
+                } else {
+                    bad = 1;
+                }
+            }
+            sg.hbase = 0;
+            sg.pbase = sg.cursor & ~15u;
+            SEG[s] = sg;
+        }
+        wave_sync();
+        stage_issue();
+        stage_commit();
+    }
+    __syncthreads();
+
+    // ---- consumer state: one column chain per lane ----------------------------
+    const uint32_t cs = lane / D, cj = lane % D;
+    uint32_t x = 0;
+    int32_t delta = 0, acc = 0;
+
+    for (uint32_t t = 0; t <= nchunks; ++t) {
+        if (!consumer && t < nchunks) {
+            const uint32_t c = t;
+            // ---- parse: lanes = (segment, candidate record) -----------------
+#pragma unroll
+            for (uint32_t pp = 0; pp < G::PPASS; ++pp) {
+                const uint32_t pr = lane + 64 * pp;
+                const uint32_t sl = pr / CB, k = pr % CB;
+                const uint32_t s = ps0 + min(sl, SPP - 1);
+                const bool here = pr < G::PAIRS;
+                const PcSeg sg = SEG[s];
+                const uint32_t bic = c * CB < sg.nblk ? min((uint32_t)CB, sg.nblk - c * CB) : 0u;
+                const uint32_t rr = sg.r + k;
+                const bool valid = here && sg.ok && rr < sg.nrec;
+                // header codes of record rr (D * HB <= 64 bits)
+                const uint32_t hp = 32 + rr * D * HB - 8 * sg.hbase;   // bit in the header window
+                const uint32_t *hw = stgw + s * NU * 4;
+                const uint32_t cw_lo = lds_bits32(hw, hp);
+                const uint32_t cw_hi = D * HB > 32 ? lds_bits32(hw, hp + 32) : 0u;
+                uint32_t total = 0;
+#pragma unroll
+                for (uint32_t jj = 0; jj < (uint32_t)D; ++jj) {
+                    const uint32_t bp = jj * HB;
+                    const uint32_t code = bp + HB <= 32 ? __builtin_amdgcn_ubfe(cw_lo, bp, HB)
+                                          : bp >= 32    ? __builtin_amdgcn_ubfe(cw_hi, bp - 32, HB)
+                                                        : __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(cw_hi, cw_lo, bp), 0, HB);
+                    total += code == (uint32_t)W - 1 ? (uint32_t)W : code;
+                }
+                const bool zero = total == 0;
+                const uint32_t size = !valid ? 0u : zero ? 2u : (ROW ? 8 * ((total + 7) >> 3) : total);
+                const uint32_t poff = sg.cursor + pc_incl<CB>(size, k) - size;   // payload byte of candidate k
+                const uint32_t pb = poff - sg.pbase;                               // byte in the payload window
+                const uint32_t *pw = hw + HU * 4;
+                const uint32_t cnt = lds_bits32(pw, 8 * pb) & 0xFFFFu;
+                const uint32_t nb = !valid ? 0u : zero ? cnt : 1u;
+                if (valid && zero && cnt == 0) bad = 1;
+                const uint32_t start = sg.rle_rem + pc_incl<CB>(nb, k) - nb;     // first block it covers
+                const bool used = valid && start < bic;
+                if (here) BM[s * CB + k] = kPcZero;
+                wave_sync();
+                if (used && !zero) {
+                    u32x4 rec;
+                    rec.x = cw_lo;
+                    rec.y = cw_hi;
+                    rec.z = 8 * ((s * NU + HU) * 16 + pb);   // payload bit in the staging array
+                    rec.w = ROW ? 8 * ((total + 7) >> 3) : 0u;
+                    REC[s * CB + k] = rec;
+                    BM[s * CB + start] = k;
+                }
+                const uint32_t n_used = pc_total<CB>(used ? 1u : 0u);
+                const uint32_t adv = pc_total<CB>(used ? size : 0u);
+                const uint32_t cov = sg.rle_rem + pc_total<CB>(used ? nb : 0u);
+                if (here && k == 0) {
+                    PcSeg ns = sg;
+                    if (bic > 0 && cov < bic) bad = 1;
+                    ns.r = sg.r + n_used;
+                    ns.cursor = sg.cursor + adv;
+                    ns.rle_rem = cov > bic ? cov - bic : 0u;
+                    ns.hbase = (4 + ((ns.r * D * HB) >> 3)) & ~15u;
+                    ns.pbase = ns.cursor & ~15u;
+                    SEG[s] = ns;
+                }
+            }
+            wave_sync();
+            // ---- stage the next chunk's windows -----------------------------
+            if (c + 1 < nchunks) stage_issue();
+            // ---- unpack: lanes = (segment, block, column) --------------------
+            uint8_t *const zbuf = zb + (c & 1) * 64 * ZSTR;
+#pragma unroll
+            for (uint32_t ip = 0; ip < G::IPASS; ++ip) {
+                const uint32_t it = lane + 64 * ip;
+                const uint32_t j = it % D, b = (it / D) % CB, sl = it / (D * CB);
+                const uint32_t s = ps0 + min(sl, SPP - 1);
+                const uint32_t k = BM[s * CB + b];
+                const bool nz = it < G::ITEMS && k != kPcZero;
+                const u32x4 rec = REC[s * CB + (k & (CB - 1))];
+                const uint32_t bp = j * HB;
+                const uint32_t code = !nz ? 0u
+                                      : bp + HB <= 32 ? __builtin_amdgcn_ubfe(rec.x, bp, HB)
+                                      : bp >= 32      ? __builtin_amdgcn_ubfe(rec.y, bp - 32, HB)
+                                                      : __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(rec.y, rec.x, bp), 0, HB);
+                const uint32_t width = code == (uint32_t)W - 1 ? (uint32_t)W : code;
+                const uint32_t off = pc_incl<D>(width, j) - width;
+                const uint32_t p0 = nz ? rec.z + (ROW ? off : 8 * off) : 0u;
+                const uint32_t step = !nz ? 0u : ROW ? rec.w : width;
+                int32_t e[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const uint32_t z = __builtin_amdgcn_ubfe(lds_bits32(stgw, p0 + (uint32_t)i * step), 0, width);
+                    e[i] = unzigzag(z);
+                }
+                if (it < G::ITEMS) {
+                    uint8_t *zp = zbuf + (s * D + j) * ZSTR + b * 8 * WB;
+                    if (WB == 2) {
+                        u32x4 v;
+                        v.x = (e[0] & 0xFFFFu) | ((uint32_t)e[1] << 16);
+                        v.y = (e[2] & 0xFFFFu) | ((uint32_t)e[3] << 16);
+                        v.z = (e[4] & 0xFFFFu) | ((uint32_t)e[5] << 16);
+                        v.w = (e[6] & 0xFFFFu) | ((uint32_t)e[7] << 16);
+                        *reinterpret_cast<u32x4 *>(zp) = v;
+                    } else {
+                        uint2 v;
+                        v.x = (e[0] & 0xFFu) | ((e[1] & 0xFFu) << 8) | ((e[2] & 0xFFu) << 16) | ((uint32_t)e[3] << 24);
+                        v.y = (e[4] & 0xFFu) | ((e[5] & 0xFFu) << 8) | ((e[6] & 0xFFu) << 16) | ((uint32_t)e[7] << 24);
+                        *reinterpret_cast<uint2 *>(zp) = v;
+                    }
+                }
+            }
+            wave_sync();
+            if (c + 1 < nchunks) stage_commit();
+        } else if (consumer && t > 0) {
+            const uint32_t c = t - 1;
+            // ---- recurrence: lane = column chain ------------------------------
+            const uint8_t *const zc = zb + (c & 1) * 64 * ZSTR + lane * ZSTR;
+            const uint32_t obase = cs * OSEG + cj * WB;
+            const uint32_t sh = g.sh;
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                uint32_t ev[4];
+                if (WB == 2) {
+                    const u32x4 v = *reinterpret_cast<const u32x4 *>(zc + 16 * b);
+                    ev[0] = v.x; ev[1] = v.y; ev[2] = v.z; ev[3] = v.w;
+                } else {
+                    const uint2 v = *reinterpret_cast<const uint2 *>(zc + 8 * b);
+                    ev[0] = v.x; ev[1] = v.y; ev[2] = 0; ev[3] = 0;
+                }
+                const int32_t alpha = acc >> sh;
+                int32_t grad = 0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    // E = e * 2^w, taken straight from the packed field
+                    int32_t E;
+                    if (WB == 2) E = (i & 1) ? (int32_t)(ev[i >> 1] & 0xFFFF0000u) : (int32_t)(ev[i >> 1] << 16);
+                    else E = __builtin_amdgcn_sbfe((int32_t)ev[i >> 2], 8 * (i & 3), 8) << 8;
+                    if (FIRE) {
+                        const int32_t tt = E + __mul24(alpha, delta);
+                        if (i & 1) grad += __mul24(sgn_med3(E), delta);
+                        delta = __builtin_amdgcn_sbfe(tt, (uint32_t)W, (uint32_t)W);
+                        x += (uint32_t)delta;
+                    } else {
+                        x += (uint32_t)(E >> W);
+                    }
+                    const uint32_t o = obase + (uint32_t)((8 * b + i) * D * WB);
+                    if (WB == 1) outb[o] = (uint8_t)x;
+                    else *reinterpret_cast<uint16_t *>(outb + o) = (uint16_t)x;
+                }
+                if (FIRE) acc = min(max(acc + grad, g.acc_lo), g.acc_hi);
+            }
+            wave_sync();
+            // ---- output: each segment's rows of this chunk ---------------------
+            const uint32_t nb = seg_blocks(cs);
+            const uint32_t bic = c * CB < nb ? min((uint32_t)CB, nb - c * CB) : 0u;
+            const uint32_t valid = bic * 8 * D * WB;
+            const uint32_t gbase = (cs * g.S + c * CB * 8) * D * WB;
+#pragma unroll
+            for (uint32_t u = 0; u < G::UPL; ++u) {
+                const uint32_t lo = 16 * (cj + u * D);
+                if (lo + 16 <= valid) {
+                    u32x4 v;
+                    if (G::WIDE) {
+                        v = *reinterpret_cast<const u32x4 *>(outb + cs * OSEG + lo);
+                    } else {
+                        const uint32_t *p = reinterpret_cast<const uint32_t *>(outb + cs * OSEG + lo);
+                        v.x = p[0]; v.y = p[1]; v.z = p[2]; v.w = p[3];
+                    }
+                    buf_st128(out, gbase + lo, v);
+                } else if (lo + 8 == valid) {
+                    const uint32_t *p = reinterpret_cast<const uint32_t *>(outb + cs * OSEG + lo);
+                    __builtin_amdgcn_raw_buffer_store_b32(p[0], out.r, gbase + lo, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(p[1], out.r, gbase + lo + 4, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- producers: raw tail rows and final checks -----------------------------
+    if (!consumer && lane < SPP) {
+        const uint32_t s = ps0 + lane;
+        const PcSeg sg = SEG[s];
+        if (sg.ok) {
+            const uint32_t tb = sg.tail * D * WB;
+            if (sg.r != sg.nrec || sg.rle_rem != 0 || sg.cursor + tb > sg.ext) {
+                bad = 1;
+            } else {
+                const uint32_t ob = (s * g.S + sg.nblk * 8) * D * WB;
+                for (uint32_t q = 0; q < tb; ++q) buf_st8(out, ob + q, buf_ld8(in, sg.ra + sg.cursor + q));
+            }
+        }
+    }
+    if (bad && status) atomicOr(status, 1);
+}
+
+}  // namespace spz

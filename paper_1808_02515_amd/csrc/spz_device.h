@@ -119,6 +119,14 @@ __device__ __forceinline__ void buf_st128(Buf b, uint32_t off, u32x4 v) {
     __builtin_amdgcn_raw_buffer_store_b128(v, b.r, off, 0, 0);
 }
 
+// Hand-off point between lanes of one wavefront through LDS: the lanes run
+// in lockstep and a wavefront's LDS accesses complete in order, so this only
+// keeps the compiler from moving memory accesses across the point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Make a value the compiler cannot prove uniform usable as a scalar operand.
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
