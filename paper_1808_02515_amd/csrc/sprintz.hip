@@ -121,14 +121,14 @@ hipError_t launch_decode(const void *src, const spz::Geom &g, void *dst, int32_t
     using T = typename spz::Elem<W>::T;
     if (g.nseg == 0) return hipGetLastError();
     if (chunked_ok(g, W, dst) && (g.D & (g.D - 1)) == 0 && g.D <= 16) {
-        const uint32_t spw = 64u / g.D;
+        const uint32_t spw = 64u * spz::kPcConsumers / g.D;
         const uint32_t grid = (g.nseg + spw - 1) / spw;
         switch (g.D) {
 #define SPZ_PC(D_)                                                                                        \
     case D_:                                                                                              \
-        hipLaunchKernelGGL((spz::k_decode_pc<W, FIRE, D_, spz::kPcProducers>), dim3(grid),                \
-                           dim3(64 * (spz::kPcProducers + 1)), 0, stream, (const uint8_t *)src, g, (T *)dst, \
-                           status);                                                                       \
+        hipLaunchKernelGGL((spz::k_decode_pc<W, FIRE, D_, spz::kPcProducers, spz::kPcConsumers>), dim3(grid), \
+                           dim3(64 * (spz::kPcProducers + spz::kPcConsumers)), 0, stream, (const uint8_t *)src, \
+                           g, (T *)dst, status);                                                          \
         break;
             SPZ_PC(1) SPZ_PC(2) SPZ_PC(4) SPZ_PC(8) SPZ_PC(16)
 #undef SPZ_PC

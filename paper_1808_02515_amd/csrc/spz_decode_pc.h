@@ -4,8 +4,9 @@
 // Paper: Algorithm 2 (decodeBlock) with the forecasters of Section 4.2. Of
 // the decoding work only the forecaster recurrence is serial (Section 5.4
 // names the dependence of each prediction on the previous sample as the
-// limit). A workgroup therefore splits into NP producer wavefronts and one
-// consumer wavefront that work on consecutive chunks at the same time:
+// limit). A workgroup therefore splits into NP producer wavefronts and NC
+// consumer wavefronts (64 column chains each) that work on consecutive chunks
+// at the same time:
 //
 //   producers (chunk t)   parse   lanes = (segment, candidate record k of the
 //                                 chunk): the record's header codes give its
@@ -42,6 +43,7 @@ namespace spz {
 
 constexpr int kPcChunkBlocks = 8;
 constexpr int kPcProducers = 2;      // producer wavefronts per workgroup
+constexpr int kPcConsumers = 1;      // consumer wavefronts per workgroup
 constexpr uint32_t kPcZero = 0xFFu;  // block map entry of a zero (run) block
 
 template <int CTRL> __device__ __forceinline__ uint32_t pc_dpp(uint32_t v) {
@@ -79,10 +81,11 @@ struct PcSeg {
     uint32_t ok, tail, pad;
 };
 
-template <int W, int D, int CB, int NP> struct PcGeom {
+template <int W, int D, int CB, int NP, int NC> struct PcGeom {
     static constexpr uint32_t HB = W == 8 ? 3 : 4;
     static constexpr uint32_t WB = W / 8;
-    static constexpr uint32_t SPW = 64 / D;                        // segments per workgroup
+    static constexpr uint32_t CHAINS = 64 * NC;                    // column chains per workgroup
+    static constexpr uint32_t SPW = CHAINS / D;                    // segments per workgroup
     static constexpr uint32_t SPP = SPW / NP;                      // segments per producer wave
     static constexpr uint32_t MAXREC = 8 * D * WB;                 // largest record payload
     static constexpr uint32_t HU = (CB * D * HB / 8 + 28 + 15) / 16;   // header window units
@@ -100,19 +103,19 @@ template <int W, int D, int CB, int NP> struct PcGeom {
     static constexpr uint32_t UPL = CB * 8 * WB / 16;              // 16-byte output units per lane
 };
 
-template <int W, bool FIRE, int D, int NP>
-__global__ __launch_bounds__(64 * (NP + 1)) void k_decode_pc(const uint8_t *__restrict__ src, Geom g,
+template <int W, bool FIRE, int D, int NP, int NC>
+__global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__restrict__ src, Geom g,
                                                             typename Elem<W>::T *__restrict__ dst,
                                                             int32_t *__restrict__ status) {
     constexpr int CB = kPcChunkBlocks;
-    using G = PcGeom<W, D, CB, NP>;
+    using G = PcGeom<W, D, CB, NP, NC>;
     constexpr uint32_t HB = G::HB, WB = G::WB, SPW = G::SPW, SPP = G::SPP, HU = G::HU, NU = G::NU;
     constexpr uint32_t ZSTR = G::ZSTR, OSEG = G::OSEG;
     constexpr bool ROW = D * W > 32;   // row-major payloads (reading R13)
     static_assert(SPP * NP == SPW && CB <= 16, "geometry");
 
     __shared__ u32x4 STG[SPW * NU];                   // [segment][header window | payload window]
-    __shared__ u32x4 ZB4[2 * 64 * ZSTR / 16];          // [buffer][chain] errors of a chunk
+    __shared__ u32x4 ZB4[2 * G::CHAINS * ZSTR / 16];   // [buffer][chain] errors of a chunk
     __shared__ uint32_t OUTW[SPW * OSEG / 4];         // [segment] output rows of a chunk
     __shared__ u32x4 REC[SPW * CB];                   // [segment][candidate]: codes lo, hi, payload bit, bits per row
     __shared__ uint32_t BM[SPW * CB];                 // [segment][block]: candidate or kPcZero
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(64 * (NP + 1)) void k_decode_pc(const uint8_t *__re
 
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid >> 6, lane = tid & 63;
-    const bool consumer = wave == NP;
+    const bool consumer = wave >= NP;
     const uint32_t seg0 = blockIdx.x * SPW;
     const uint32_t nsw = min(SPW, g.nseg - seg0);
 
@@ -132,6 +135,12 @@ __global__ __launch_bounds__(64 * (NP + 1)) void k_decode_pc(const uint8_t *__re
     auto tab_ld = [&](uint32_t k) -> uint64_t {
         return (uint64_t)buf_ld32(tab, 8 * k) | ((uint64_t)buf_ld32(tab, 8 * k + 4) << 32);
     };
+    // every offset-table entry this workgroup needs, in one round trip
+    const uint32_t ps0 = (consumer ? 0u : wave) * SPP;   // a producer's first segment
+    const uint32_t my_s = ps0 + lane;
+    const bool my_seg = !consumer && lane < SPP && my_s < nsw;
+    uint64_t my_a = 0, my_b = 0;
+    if (my_seg) { my_a = tab_ld(seg0 + my_s); my_b = tab_ld(seg0 + my_s + 1); }
     const uint64_t a_wg = uniform64(tab_ld(seg0));
     const uint64_t b_wg = uniform64(tab_ld(seg0 + nsw));
     const bool wg_ok = a_wg <= b_wg && b_wg <= g.data_bytes && b_wg - a_wg <= 0x7FFFFFF0ull;
@@ -146,7 +155,6 @@ __global__ __launch_bounds__(64 * (NP + 1)) void k_decode_pc(const uint8_t *__re
     uint32_t bad = 0;
 
     // ---- producer: segment setup and the first chunk's windows ---------------
-    const uint32_t ps0 = wave * SPP;   // this producer's first segment
     u32x4 reg[G::SPASS];
     auto stage_issue = [&]() {
 #pragma unroll
@@ -170,13 +178,13 @@ __global__ __launch_bounds__(64 * (NP + 1)) void k_decode_pc(const uint8_t *__re
     };
     if (!consumer) {
         if (lane < SPP) {
-            const uint32_t s = ps0 + lane;
+            const uint32_t s = my_s;
             PcSeg sg;
             sg.ra = 0; sg.ext = 0; sg.nrec = 0; sg.nblk = 0; sg.r = 0; sg.cursor = 4; sg.rle_rem = 0;
             sg.ok = 0; sg.tail = 0; sg.pad = 0;
-            if (s < nsw) {
+            if (my_seg) {
                 const uint32_t seg = seg0 + s;
-                const uint64_t a = tab_ld(seg), b = tab_ld(seg + 1);
+                const uint64_t a = my_a, b = my_b;
                 const uint32_t nr = (uint32_t)min((uint64_t)g.S, g.rows - (uint64_t)seg * g.S);
                 sg.tail = nr & 7u;
                 if (wg_ok && a_wg <= a && a <= b && b <= b_wg && !((a | b) & 15u) && b - a >= 16) {
@@ -203,7 +211,8 @@ __global__ __launch_bounds__(64 * (NP + 1)) void k_decode_pc(const uint8_t *__re
     __syncthreads();
 
     // ---- consumer state: one column chain per lane ----------------------------
-    const uint32_t cs = lane / D, cj = lane % D;
+    const uint32_t chain = (wave - NP) * 64 + lane;   // consumers only
+    const uint32_t cs = chain / D, cj = chain % D;
     uint32_t x = 0;
     int32_t delta = 0, acc = 0;
 
@@ -274,15 +283,32 @@ __global__ __launch_bounds__(64 * (NP + 1)) void k_decode_pc(const uint8_t *__re
             // ---- stage the next chunk's windows -----------------------------
             if (c + 1 < nchunks) stage_issue();
             // ---- unpack: lanes = (segment, block, column) --------------------
-            uint8_t *const zbuf = zb + (c & 1) * 64 * ZSTR;
+            // All LDS reads of the chunk's items are issued in three batches
+            // (block map, records, fields) so that their latency is paid
+            // three times per chunk rather than three times per item.
+            uint8_t *const zbuf = zb + (c & 1) * G::CHAINS * ZSTR;
+            constexpr uint32_t IP = G::IPASS;
+            uint32_t kk[IP];
 #pragma unroll
-            for (uint32_t ip = 0; ip < G::IPASS; ++ip) {
+            for (uint32_t ip = 0; ip < IP; ++ip) {
                 const uint32_t it = lane + 64 * ip;
-                const uint32_t j = it % D, b = (it / D) % CB, sl = it / (D * CB);
-                const uint32_t s = ps0 + min(sl, SPP - 1);
-                const uint32_t k = BM[s * CB + b];
-                const bool nz = it < G::ITEMS && k != kPcZero;
-                const u32x4 rec = REC[s * CB + (k & (CB - 1))];
+                const uint32_t b = (it / D) % CB, s = ps0 + min(it / (D * CB), SPP - 1);
+                kk[ip] = BM[s * CB + b];
+            }
+            u32x4 rr[IP];
+#pragma unroll
+            for (uint32_t ip = 0; ip < IP; ++ip) {
+                const uint32_t it = lane + 64 * ip;
+                const uint32_t s = ps0 + min(it / (D * CB), SPP - 1);
+                rr[ip] = REC[s * CB + (kk[ip] & (CB - 1))];
+            }
+            uint32_t fw[IP][8][2], wd[IP];
+#pragma unroll
+            for (uint32_t ip = 0; ip < IP; ++ip) {
+                const uint32_t it = lane + 64 * ip;
+                const uint32_t j = it % D;
+                const bool nz = it < G::ITEMS && kk[ip] != kPcZero;
+                const u32x4 rec = rr[ip];
                 const uint32_t bp = j * HB;
                 const uint32_t code = !nz ? 0u
                                       : bp + HB <= 32 ? __builtin_amdgcn_ubfe(rec.x, bp, HB)
@@ -292,12 +318,23 @@ __global__ __launch_bounds__(64 * (NP + 1)) void k_decode_pc(const uint8_t *__re
                 const uint32_t off = pc_incl<D>(width, j) - width;
                 const uint32_t p0 = nz ? rec.z + (ROW ? off : 8 * off) : 0u;
                 const uint32_t step = !nz ? 0u : ROW ? rec.w : width;
-                int32_t e[8];
+                wd[ip] = width;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    const uint32_t z = __builtin_amdgcn_ubfe(lds_bits32(stgw, p0 + (uint32_t)i * step), 0, width);
-                    e[i] = unzigzag(z);
+                    const uint32_t p = p0 + (uint32_t)i * step;
+                    const uint32_t *q = stgw + (p >> 5);
+                    fw[ip][i][0] = q[0];
+                    fw[ip][i][1] = q[1];
+                    fw[ip][i][0] = __builtin_amdgcn_alignbit(fw[ip][i][1], fw[ip][i][0], p);
                 }
+            }
+#pragma unroll
+            for (uint32_t ip = 0; ip < IP; ++ip) {
+                const uint32_t it = lane + 64 * ip;
+                const uint32_t j = it % D, b = (it / D) % CB, s = ps0 + min(it / (D * CB), SPP - 1);
+                int32_t e[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) e[i] = unzigzag(__builtin_amdgcn_ubfe(fw[ip][i][0], 0, wd[ip]));
                 if (it < G::ITEMS) {
                     uint8_t *zp = zbuf + (s * D + j) * ZSTR + b * 8 * WB;
                     if (WB == 2) {
@@ -320,19 +357,25 @@ __global__ __launch_bounds__(64 * (NP + 1)) void k_decode_pc(const uint8_t *__re
         } else if (consumer && t > 0) {
             const uint32_t c = t - 1;
             // ---- recurrence: lane = column chain ------------------------------
-            const uint8_t *const zc = zb + (c & 1) * 64 * ZSTR + lane * ZSTR;
+            const uint8_t *const zc = zb + (c & 1) * G::CHAINS * ZSTR + chain * ZSTR;
             const uint32_t obase = cs * OSEG + cj * WB;
             const uint32_t sh = g.sh;
+            // the whole chunk's errors first: one LDS wait per chunk
+            uint32_t evs[CB][4];
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
-                uint32_t ev[4];
                 if (WB == 2) {
                     const u32x4 v = *reinterpret_cast<const u32x4 *>(zc + 16 * b);
-                    ev[0] = v.x; ev[1] = v.y; ev[2] = v.z; ev[3] = v.w;
+                    evs[b][0] = v.x; evs[b][1] = v.y; evs[b][2] = v.z; evs[b][3] = v.w;
                 } else {
                     const uint2 v = *reinterpret_cast<const uint2 *>(zc + 8 * b);
-                    ev[0] = v.x; ev[1] = v.y; ev[2] = 0; ev[3] = 0;
+                    evs[b][0] = v.x; evs[b][1] = v.y; evs[b][2] = 0; evs[b][3] = 0;
                 }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                const uint32_t *const ev = evs[b];
                 const int32_t alpha = acc >> sh;
                 int32_t grad = 0;
 #pragma unroll
@@ -383,18 +426,18 @@ __global__ __launch_bounds__(64 * (NP + 1)) void k_decode_pc(const uint8_t *__re
         __syncthreads();
     }
 
-    // ---- producers: raw tail rows and final checks -----------------------------
-    if (!consumer && lane < SPP) {
-        const uint32_t s = ps0 + lane;
-        const PcSeg sg = SEG[s];
-        if (sg.ok) {
+    // ---- producers: final checks and raw tail rows (a stream's last segment) ----
+    if (!consumer) {
+        for (uint32_t s = ps0; s < ps0 + SPP; ++s) {
+            const PcSeg sg = SEG[s];
             const uint32_t tb = sg.tail * D * WB;
+            if (!sg.ok) continue;
             if (sg.r != sg.nrec || sg.rle_rem != 0 || sg.cursor + tb > sg.ext) {
                 bad = 1;
-            } else {
-                const uint32_t ob = (s * g.S + sg.nblk * 8) * D * WB;
-                for (uint32_t q = 0; q < tb; ++q) buf_st8(out, ob + q, buf_ld8(in, sg.ra + sg.cursor + q));
+                continue;
             }
+            const uint32_t ob = (s * g.S + sg.nblk * 8) * D * WB;
+            for (uint32_t q = lane; q < tb; q += 64) buf_st8(out, ob + q, buf_ld8(in, sg.ra + sg.cursor + q));
         }
     }
     if (bad && status) atomicOr(status, 1);
