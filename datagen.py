@@ -136,3 +136,109 @@ def batch_stream(k: int, max_rows: int | None = None) -> np.ndarray:
     if dt == np.int8:
         return walk_int8(rows, D, sigma=sigma, seed=3_000_000 + k)
     return ar2_uint16(rows, D, sigma=sigma, seed=3_000_000 + k)
+
+
+# ---------------------------------------------------------------------------
+# The same recipes drawn on a GPU with torch (seeded torch generators; the
+# numbers differ from the numpy draws above, the distributions do not). Used
+# for the 10,000-stream batch workload, whose 13.5 GB would take an hour to
+# draw on the CPU.
+# ---------------------------------------------------------------------------
+def _torch_run_mask(n: int, coverage: float, gen, device, lo: int = 8, hi: int = 256):
+    """Boolean mask of runs of U{lo..hi} positions at uniform random starts,
+    added in rounds until at least ``coverage`` of n is covered."""
+    import torch
+    mask = torch.zeros(n, dtype=torch.bool, device=device)
+    if n == 0 or coverage <= 0:
+        return mask
+    while int(mask.sum().item()) < coverage * n:
+        need = coverage * n - int(mask.sum().item())
+        m = max(1, int(need / ((lo + hi) / 2)) + 1)
+        starts = torch.randint(0, n, (m,), generator=gen, device=device)
+        lens = torch.randint(lo, hi + 1, (m,), generator=gen, device=device)
+        diff = torch.zeros(n + 1, dtype=torch.int32, device=device)
+        diff.index_add_(0, starts, torch.ones(m, dtype=torch.int32, device=device))
+        diff.index_add_(0, torch.clamp(starts + lens, max=n), -torch.ones(m, dtype=torch.int32, device=device))
+        mask |= torch.cumsum(diff[:n], 0) > 0
+    return mask
+
+
+def clipped_walk_torch(steps, lo: int, hi: int):
+    """x_t = clip(x_{t-1} + steps_t, lo, hi) from x_{-1} = 0 along dim 0, by a
+    Hillis-Steele scan over the maps x -> clip(x + a, l, h), which compose as
+    (a1, l1, h1) then (a2, l2, h2) = (a1 + a2, clip(l1 + a2, l2, h2),
+    clip(h1 + a2, l2, h2))."""
+    import torch
+    a = steps.to(torch.int64)
+    L = torch.full_like(a, lo)
+    H = torch.full_like(a, hi)
+    n = a.shape[0]
+    d = 1
+    while d < n:
+        a2, L2, H2 = a[d:], L[d:], H[d:]
+        a1, L1, H1 = a[:-d], L[:-d], H[:-d]
+        na = a1 + a2
+        nL = torch.minimum(torch.maximum(L1 + a2, L2), H2)
+        nH = torch.minimum(torch.maximum(H1 + a2, L2), H2)
+        a = torch.cat([a[:d], na])
+        L = torch.cat([L[:d], nL])
+        H = torch.cat([H[:d], nH])
+        d *= 2
+    return torch.minimum(torch.maximum(a, L), H)
+
+
+def walk_int8_torch(rows: int, D: int, sigma: float, const_frac: float, gen, device):
+    import torch
+    steps = torch.round(torch.randn((rows, D), generator=gen, device=device) * sigma)
+    mask = _torch_run_mask(rows, const_frac, gen, device)
+    steps[mask] = 0
+    return clipped_walk_torch(steps, -128, 127).to(torch.int8).contiguous()
+
+
+def ar2_filter_torch(e):
+    """y_t = 1.6 y_{t-1} - 0.7 y_{t-2} + e_t along dim 0 from y = 0 (float64),
+    as an inclusive Hillis-Steele scan of the state s_t = (y_t, y_{t-1}) =
+    A s_{t-1} + (e_t, 0): after step j, v_t = sum_{k < 2^j} A^k u_{t-k}."""
+    import torch
+    n = e.shape[0]
+    v0 = e.to(torch.float64)                 # first state component
+    v1 = torch.zeros_like(v0)                # second state component
+    P = [[1.6, -0.7], [1.0, 0.0]]            # A^(2^j)
+    d = 1
+    while d < n:
+        a, b, c, dd = P[0][0], P[0][1], P[1][0], P[1][1]
+        s0 = a * v0[:-d] + b * v1[:-d]
+        s1 = c * v0[:-d] + dd * v1[:-d]
+        v0 = torch.cat([v0[:d], v0[d:] + s0])
+        v1 = torch.cat([v1[:d], v1[d:] + s1])
+        P = [[a * a + b * c, a * b + b * dd], [c * a + dd * c, c * b + dd * dd]]
+        d *= 2
+    return v0
+
+
+def ar2_uint16_torch(rows: int, D: int, sigma: float, flat_frac: float, gen, device):
+    import torch
+    burn = 256   # the filter forgets its zero start: |root| = 0.837, 0.837^256 < 1e-19
+    e = torch.randn((rows + burn, D), generator=gen, device=device, dtype=torch.float64) * sigma
+    y = ar2_filter_torch(e)[burn:]
+    x = torch.clamp(torch.round(y) + 32768, 0, 65535).to(torch.int32)
+    flat = _torch_run_mask(rows, flat_frac, gen, device)
+    if rows:
+        idx = torch.arange(rows, device=device)
+        idx = torch.where(flat, torch.zeros_like(idx), idx)
+        idx = torch.cummax(idx, 0).values
+        x = x[idx]
+    return x.to(torch.int16).contiguous()   # uint16 bit patterns
+
+
+def batch_stream_torch(k: int, device="cuda"):
+    """Stream k of the batch workload drawn on the GPU (same rows, D, dtype
+    and sigma as ``batch_stream_params(k)``); uint16 streams come back as
+    int16 tensors holding the uint16 bit patterns."""
+    import torch
+    rows, D, dt, sigma = batch_stream_params(k)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(3_000_000 + k)
+    if dt == np.int8:
+        return walk_int8_torch(rows, D, sigma, 0.15, gen, device)
+    return ar2_uint16_torch(rows, D, sigma, 0.20, gen, device)

@@ -119,6 +119,48 @@ spz_status sprintz_get_info(const void *h_src, size_t n, spz_info *out);
 spz_status sprintz_decompress(const void *d_src, size_t src_size, const spz_info *info, void *d_dst,
                               size_t dst_cap, int32_t *d_status, hipStream_t stream);
 
+/* ---- Batched decompression ------------------------------------------------
+ *
+ * Decodes many containers (streams) in one go. The segments of all streams
+ * become one work list per class (w, forecaster, D); for each class one
+ * persistent grid of workgroups pulls groups of segments from a device queue,
+ * so thousands of small and large streams fill the GPU together instead of
+ * one launch each (the paper's method is unchanged: every segment is decoded
+ * exactly as by sprintz_decompress, Algorithm 2 per record).
+ *
+ * Streams outside the batched kernels (hdr_group != 0, D not in
+ * {1, 2, 4, 8, 16}, output not 16-byte aligned, seg_rows * D * w/8 not a
+ * multiple of 16) are decoded by the single-container path inside the same
+ * call. */
+typedef struct {
+    const void *d_src;   /* container, 16-byte aligned, src_size bytes */
+    size_t src_size;
+    void *d_dst;         /* output rows (rows, D); dst_cap bytes */
+    size_t dst_cap;
+} spz_batch_item;
+
+/* Opaque plan: device copies of the stream descriptors and work lists. */
+typedef struct spz_batch spz_batch;
+
+/* Validate n items (infos[i] from sprintz_get_info of item i) and build a
+ * plan. Allocates device memory (hipMalloc) and copies the work lists to it
+ * synchronously; returns the first item's error (SPZ_EINVAL, SPZ_ENOSPC,
+ * SPZ_EUNSUPPORTED) if any item is invalid, SPZ_ENOMEM / SPZ_EHIP on
+ * allocation or copy failure. The plan keeps the item pointers; the caller
+ * keeps the buffers alive and unchanged in size while the plan is used. */
+spz_status sprintz_batch_create(const spz_batch_item *items, const spz_info *infos, uint32_t n, spz_batch **out);
+
+/* Enqueue the decoding of every item of the plan on `stream`: a tiny kernel
+ * resets the per-class queues, then one launch per nonempty class, then the
+ * fallback streams. d_status: n int32 device words (zero on entry, or NULL);
+ * corrupt data in item i sets bit 1 of d_status[i]. Allocates nothing and
+ * never synchronizes, so the call can be captured into a HIP graph. Calls
+ * that overlap on one plan race on its queues. */
+spz_status sprintz_batch_decompress(const spz_batch *b, int32_t *d_status, hipStream_t stream);
+
+/* Free a plan (NULL is ignored). The caller makes sure no enqueued work uses it. */
+void sprintz_batch_destroy(spz_batch *b);
+
 /* Static description of a status code. */
 const char *sprintz_strerror(spz_status s);
 

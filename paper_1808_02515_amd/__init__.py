@@ -43,6 +43,11 @@ class SprintzError(RuntimeError):
 _lib = None
 
 #: C entry points and their ctypes signatures (also checked by the CPU tests).
+class spz_batch_item(ctypes.Structure):
+    _fields_ = [("d_src", ctypes.c_void_p), ("src_size", ctypes.c_size_t),
+                ("d_dst", ctypes.c_void_p), ("dst_cap", ctypes.c_size_t)]
+
+
 _SIGNATURES = {
     "spz_params_default": (None, [ctypes.POINTER(spz_params)]),
     "sprintz_compress_bound": (ctypes.c_size_t, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
@@ -56,6 +61,10 @@ _SIGNATURES = {
     "sprintz_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(spz_info)]),
     "sprintz_decompress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(spz_info),
                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
+    "sprintz_batch_create": (ctypes.c_int, [ctypes.POINTER(spz_batch_item), ctypes.POINTER(spz_info),
+                                            ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
+    "sprintz_batch_decompress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sprintz_batch_destroy": (None, [ctypes.c_void_p]),
     "sprintz_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sprintz_format_version": (ctypes.c_int, []),
 }
@@ -121,6 +130,27 @@ def sprintz_get_info(h_src: bytes) -> spz_info:
 def sprintz_decompress(d_src: int, src_size: int, info: spz_info, d_dst: int, dst_cap: int, d_status: int,
                        stream: int) -> int:
     return int(load().sprintz_decompress(d_src, src_size, ctypes.byref(info), d_dst, dst_cap, d_status, stream))
+
+
+def sprintz_batch_create(items, infos) -> int:
+    """items: sequence of spz_batch_item, infos: sequence of spz_info; returns
+    the plan handle (an integer)."""
+    n = len(items)
+    arr_i = (spz_batch_item * max(n, 1))(*items)
+    arr_f = (spz_info * max(n, 1))(*infos)
+    h = ctypes.c_void_p()
+    rc = load().sprintz_batch_create(arr_i, arr_f, n, ctypes.byref(h))
+    if rc != SPZ_OK:
+        raise SprintzError(rc, "sprintz_batch_create")
+    return h.value
+
+
+def sprintz_batch_decompress(plan: int, d_status: int, stream: int) -> int:
+    return int(load().sprintz_batch_decompress(plan, d_status, stream))
+
+
+def sprintz_batch_destroy(plan: int) -> None:
+    load().sprintz_batch_destroy(plan)
 
 
 def sprintz_strerror(status: int) -> str:
@@ -236,3 +266,42 @@ def decompress(container, out=None, stream=None, check: bool = True):
         if int(status.item()) != 0:
             raise SprintzError(SPZ_ECORRUPT, f"device status {int(status.item())}")
     return out
+
+
+class BatchDecoder:
+    """A decompression plan over many containers: one call decodes them all
+    (per-class persistent launches over a device work list of segments).
+
+    containers: uint8 CUDA tensors; outs: matching (rows, D) CUDA tensors
+    (allocated here when None). The plan keeps pointers to both: keep them
+    alive while it is used."""
+
+    def __init__(self, containers, outs=None, device="cuda"):
+        torch = _torch()
+        self.containers = list(containers)
+        self.infos = [info_of(c) for c in self.containers]
+        if outs is None:
+            outs = [torch.empty((i.rows, i.D), dtype=torch_dtype(i.dtype), device=device) for i in self.infos]
+        self.outs = list(outs)
+        items = [spz_batch_item(c.data_ptr(), c.numel(), o.data_ptr(), o.numel() * o.element_size())
+                 for c, o in zip(self.containers, self.outs)]
+        self.status = torch.zeros(max(len(items), 1), dtype=torch.int32, device=device)
+        self.plan = sprintz_batch_create(items, self.infos)
+
+    def run(self, stream=None, status=None):
+        """Enqueue the decoding of every container (asynchronous)."""
+        st = self.status if status is None else status
+        rc = sprintz_batch_decompress(self.plan, st.data_ptr(), _stream_handle(stream))
+        if rc != SPZ_OK:
+            raise SprintzError(rc, "sprintz_batch_decompress")
+
+    def close(self):
+        if getattr(self, "plan", None):
+            sprintz_batch_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

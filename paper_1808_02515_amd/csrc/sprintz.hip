@@ -8,6 +8,10 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+#include <new>
+#include <vector>
+
 #include "sprintz.h"
 #include "spz_decode.h"
 #include "spz_decode_chunked.h"
@@ -255,8 +259,13 @@ spz_status sprintz_get_info(const void *h_src, size_t n, spz_info *out) {
     return SPZ_OK;
 }
 
-spz_status sprintz_decompress(const void *d_src, size_t src_size, const spz_info *info, void *d_dst,
-                              size_t dst_cap, int32_t *d_status, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// Checks one decompression request; on success fills the launch geometry.
+spz_status check_decompress(const void *d_src, size_t src_size, const spz_info *info, const void *d_dst,
+                            size_t dst_cap, spz::Geom *g) {
     if (!info || !d_src) return SPZ_EINVAL;
     const uint32_t w = info->w;
     if (w != 8 && w != 16) return SPZ_EINVAL;
@@ -268,23 +277,229 @@ spz_status sprintz_decompress(const void *d_src, size_t src_size, const spz_info
     if (dst_cap < info->rows * info->D * (w / 8)) return SPZ_ENOSPC;
     if (info->rows > 0 && !d_dst) return SPZ_EINVAL;
     if (((uintptr_t)d_src & 15) || ((uintptr_t)d_dst & (w / 8 - 1))) return SPZ_EINVAL;
-    spz::Geom g = make_geom(info->rows, info->D, w, info->params.seg_rows, info->params.hdr_group,
-                            info->params.learn_shift);
-    g.cap = src_size;
-    g.data_bytes = info->compressed_size - g.data_start;
+    *g = make_geom(info->rows, info->D, w, info->params.seg_rows, info->params.hdr_group, info->params.learn_shift);
+    g->cap = src_size;
+    g->data_bytes = info->compressed_size - g->data_start;
+    return SPZ_OK;
+}
+
+hipError_t launch_decode_any(const void *d_src, const spz_info *info, const spz::Geom &g, void *d_dst,
+                             int32_t *d_status, hipStream_t stream) {
+    const uint32_t w = info->w;
     const bool col = (uint64_t)info->D * w <= 32;
     const bool fire = info->params.forecaster == SPZ_FIRE;
-    hipError_t e;
 #define SPZ_DEC(W_, F_, C_) launch_decode<W_, F_, C_>(d_src, g, d_dst, d_status, stream)
     if (w == 8) {
-        if (fire) e = col ? SPZ_DEC(8, true, true) : SPZ_DEC(8, true, false);
-        else e = col ? SPZ_DEC(8, false, true) : SPZ_DEC(8, false, false);
-    } else {
-        if (fire) e = col ? SPZ_DEC(16, true, true) : SPZ_DEC(16, true, false);
-        else e = col ? SPZ_DEC(16, false, true) : SPZ_DEC(16, false, false);
+        if (fire) return col ? SPZ_DEC(8, true, true) : SPZ_DEC(8, true, false);
+        return col ? SPZ_DEC(8, false, true) : SPZ_DEC(8, false, false);
     }
+    if (fire) return col ? SPZ_DEC(16, true, true) : SPZ_DEC(16, true, false);
+    return col ? SPZ_DEC(16, false, true) : SPZ_DEC(16, false, false);
 #undef SPZ_DEC
-    return e == hipSuccess ? SPZ_OK : SPZ_EHIP;
+}
+
+// Batched decoding: the workgroup kernels of one class (w, forecaster, D)
+// share one compiled form; a plan holds one work list per class.
+constexpr int kClasses = 2 * 2 * 5;   // w in {8, 16} x forecaster x D in {1, 2, 4, 8, 16}
+int class_of(uint32_t w, bool fire, uint32_t D) {
+    int d = D == 1 ? 0 : D == 2 ? 1 : D == 4 ? 2 : D == 8 ? 3 : 4;
+    return ((w == 16) * 2 + fire) * 5 + d;
+}
+uint32_t class_D(int c) { return 1u << (c % 5); }
+uint32_t class_w(int c) { return (c / 10) ? 16 : 8; }
+bool class_fire(int c) { return (c / 5) % 2; }
+
+template <int W, bool FIRE, int D>
+hipError_t launch_batch_class(const spz::PcStream *streams, const uint64_t *entries, const uint32_t *group_s,
+                              uint32_t ngroups, uint32_t *queue, int32_t *status, uint32_t grid, hipStream_t stream) {
+    hipLaunchKernelGGL((spz::k_decode_pc_batch<W, FIRE, D, spz::kPcProducers, spz::kPcConsumers>), dim3(grid),
+                       dim3(64 * (spz::kPcProducers + spz::kPcConsumers)), 0, stream, streams, entries, group_s,
+                       ngroups, queue, status);
+    return hipGetLastError();
+}
+
+template <int W, bool FIRE, int D>
+uint32_t batch_grid_cap() {
+    // resident workgroups of this kernel on the current device (1 if the query fails)
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, (const void *)spz::k_decode_pc_batch<W, FIRE, D, spz::kPcProducers, spz::kPcConsumers>,
+            64 * (spz::kPcProducers + spz::kPcConsumers), 0) != hipSuccess)
+        return 1;
+    return (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)(cus > 0 ? cus : 1);
+}
+
+}  // namespace
+
+struct spz_batch {
+    uint32_t n;
+    void *dmem;                                    // one device allocation for everything below
+    spz::PcStream *streams;
+    uint64_t *entries[kClasses];
+    uint32_t *group_s[kClasses];
+    uint32_t ngroups[kClasses];
+    uint32_t grid[kClasses];
+    uint32_t *queues;                              // one work counter per class
+    // streams that take the single-container path
+    struct Fallback { const void *src; void *dst; spz_info info; spz::Geom g; uint32_t index; };
+    Fallback *fallback;
+    uint32_t nfallback;
+};
+
+extern "C" {
+
+spz_status sprintz_decompress(const void *d_src, size_t src_size, const spz_info *info, void *d_dst,
+                              size_t dst_cap, int32_t *d_status, hipStream_t stream) {
+    spz::Geom g;
+    const spz_status st = check_decompress(d_src, src_size, info, d_dst, dst_cap, &g);
+    if (st != SPZ_OK) return st;
+    return launch_decode_any(d_src, info, g, d_dst, d_status, stream) == hipSuccess ? SPZ_OK : SPZ_EHIP;
+}
+
+spz_status sprintz_batch_create(const spz_batch_item *items, const spz_info *infos, uint32_t n, spz_batch **out) {
+    if (!out || (n > 0 && (!items || !infos))) return SPZ_EINVAL;
+    *out = nullptr;
+    spz_batch *b = new (std::nothrow) spz_batch();
+    if (!b) return SPZ_ENOMEM;
+    b->n = n;
+    std::vector<spz::Geom> geoms(n);
+    std::vector<int> cls(n, -1);
+    for (uint32_t i = 0; i < n; ++i) {
+        const spz_status st =
+            check_decompress(items[i].d_src, items[i].src_size, &infos[i], items[i].d_dst, items[i].dst_cap, &geoms[i]);
+        if (st != SPZ_OK) { delete b; return st; }
+        const spz_info &in = infos[i];
+        const uint32_t D = in.D;
+        const bool pow2 = (D & (D - 1)) == 0 && D <= 16;
+        if (pow2 && in.params.hdr_group == 0 && !((uintptr_t)items[i].d_dst & 15) &&
+            ((uint64_t)in.params.seg_rows * D * (in.w / 8)) % 16 == 0 && in.nseg > 0)
+            cls[i] = class_of(in.w, in.params.forecaster == SPZ_FIRE, D);
+    }
+    // work lists: per class, streams ordered by seg_rows so that a group of
+    // segments never mixes two seg_rows; a group holds 64 * consumers / D entries
+    std::vector<std::vector<uint64_t>> ent(kClasses);
+    std::vector<std::vector<uint32_t>> gs(kClasses);
+    std::vector<uint32_t> order(n);
+    for (uint32_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        return infos[x].params.seg_rows < infos[y].params.seg_rows;
+    });
+    std::vector<spz_batch::Fallback> fb;
+    for (uint32_t oi = 0; oi < n; ++oi) {
+        const uint32_t i = order[oi];
+        if (cls[i] < 0) {
+            if (infos[i].rows > 0) fb.push_back({items[i].d_src, items[i].d_dst, infos[i], geoms[i], i});
+            continue;
+        }
+        const int c = cls[i];
+        const uint32_t spw = 64u * spz::kPcConsumers / class_D(c);
+        const uint32_t S = infos[i].params.seg_rows;
+        for (uint32_t sg = 0; sg < infos[i].nseg; ++sg) {
+            if (ent[c].size() % spw == 0 || gs[c].back() != S) {
+                while (ent[c].size() % spw) ent[c].push_back(~0ull);
+                gs[c].push_back(S);
+            }
+            ent[c].push_back(((uint64_t)i << 32) | sg);
+        }
+    }
+    size_t bytes = sizeof(spz::PcStream) * (size_t)n + 16 + sizeof(uint32_t) * kClasses;
+    for (int c = 0; c < kClasses; ++c) {
+        const uint32_t spw = 64u * spz::kPcConsumers / class_D(c);
+        while (ent[c].size() % spw) ent[c].push_back(~0ull);
+        bytes += ent[c].size() * 8 + gs[c].size() * 4 + 16;
+    }
+    if (hipMalloc(&b->dmem, bytes) != hipSuccess) { delete b; return SPZ_ENOMEM; }
+    std::vector<uint8_t> host(bytes, 0);
+    size_t off = 0;
+    auto carve = [&](size_t sz) { const size_t o = off; off = (off + sz + 15) & ~size_t(15); return o; };
+    const size_t o_streams = carve(sizeof(spz::PcStream) * (size_t)n);
+    spz::PcStream *hs = reinterpret_cast<spz::PcStream *>(host.data() + o_streams);
+    for (uint32_t i = 0; i < n; ++i) {
+        const spz_info &in = infos[i];
+        const spz::Geom &g = geoms[i];
+        spz::PcStream &st = hs[i];
+        st.src = (const uint8_t *)items[i].d_src;
+        st.dst = (uint8_t *)items[i].d_dst;
+        st.data_start = g.data_start;
+        st.data_bytes = g.data_bytes;
+        st.rows = in.rows;
+        st.nseg = in.nseg;
+        st.S = in.params.seg_rows;
+        st.sh = g.sh;
+        st.acc_lo = g.acc_lo;
+        st.acc_hi = g.acc_hi;
+        st.pad = 0;
+    }
+    size_t o_ent[kClasses], o_gs[kClasses];
+    for (int c = 0; c < kClasses; ++c) {
+        o_ent[c] = carve(ent[c].size() * 8);
+        if (!ent[c].empty()) memcpy(host.data() + o_ent[c], ent[c].data(), ent[c].size() * 8);
+        o_gs[c] = carve(gs[c].size() * 4);
+        if (!gs[c].empty()) memcpy(host.data() + o_gs[c], gs[c].data(), gs[c].size() * 4);
+    }
+    const size_t o_q = carve(sizeof(uint32_t) * kClasses);
+    if (hipMemcpy(b->dmem, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(b->dmem);
+        delete b;
+        return SPZ_EHIP;
+    }
+    uint8_t *base = (uint8_t *)b->dmem;
+    b->streams = (spz::PcStream *)(base + o_streams);
+    b->queues = (uint32_t *)(base + o_q);
+    for (int c = 0; c < kClasses; ++c) {
+        b->entries[c] = (uint64_t *)(base + o_ent[c]);
+        b->group_s[c] = (uint32_t *)(base + o_gs[c]);
+        b->ngroups[c] = (uint32_t)gs[c].size();
+        uint32_t cap = 1;
+#define SPZ_CAP(W_, F_, D_) if (class_w(c) == W_ && class_fire(c) == F_ && class_D(c) == D_) cap = batch_grid_cap<W_, F_, D_>();
+#define SPZ_CAPD(W_, F_) SPZ_CAP(W_, F_, 1) SPZ_CAP(W_, F_, 2) SPZ_CAP(W_, F_, 4) SPZ_CAP(W_, F_, 8) SPZ_CAP(W_, F_, 16)
+        if (b->ngroups[c]) { SPZ_CAPD(8, false) SPZ_CAPD(8, true) SPZ_CAPD(16, false) SPZ_CAPD(16, true) }
+#undef SPZ_CAPD
+#undef SPZ_CAP
+        b->grid[c] = std::min(b->ngroups[c], cap);
+    }
+    b->nfallback = (uint32_t)fb.size();
+    b->fallback = nullptr;
+    if (!fb.empty()) {
+        b->fallback = new (std::nothrow) spz_batch::Fallback[fb.size()];
+        if (!b->fallback) { (void)hipFree(b->dmem); delete b; return SPZ_ENOMEM; }
+        std::copy(fb.begin(), fb.end(), b->fallback);
+    }
+    *out = b;
+    return SPZ_OK;
+}
+
+spz_status sprintz_batch_decompress(const spz_batch *b, int32_t *d_status, hipStream_t stream) {
+    if (!b) return SPZ_EINVAL;
+    hipLaunchKernelGGL(spz::k_zero_u32, dim3(1), dim3(64), 0, stream, b->queues, (uint32_t)kClasses);
+    for (int c = 0; c < kClasses; ++c) {
+        if (!b->ngroups[c]) continue;
+        hipError_t e = hipSuccess;
+#define SPZ_BL(W_, F_, D_)                                                                                      \
+    if (class_w(c) == W_ && class_fire(c) == F_ && class_D(c) == D_)                                            \
+        e = launch_batch_class<W_, F_, D_>(b->streams, b->entries[c], b->group_s[c], b->ngroups[c], b->queues + c, \
+                                           d_status, b->grid[c], stream);
+#define SPZ_BLD(W_, F_) SPZ_BL(W_, F_, 1) SPZ_BL(W_, F_, 2) SPZ_BL(W_, F_, 4) SPZ_BL(W_, F_, 8) SPZ_BL(W_, F_, 16)
+        SPZ_BLD(8, false) SPZ_BLD(8, true) SPZ_BLD(16, false) SPZ_BLD(16, true)
+#undef SPZ_BLD
+#undef SPZ_BL
+        if (e != hipSuccess) return SPZ_EHIP;
+    }
+    for (uint32_t k = 0; k < b->nfallback; ++k) {
+        const spz_batch::Fallback &f = b->fallback[k];
+        if (launch_decode_any(f.src, &f.info, f.g, f.dst, d_status ? d_status + f.index : nullptr, stream) != hipSuccess)
+            return SPZ_EHIP;
+    }
+    return hipGetLastError() == hipSuccess ? SPZ_OK : SPZ_EHIP;
+}
+
+void sprintz_batch_destroy(spz_batch *b) {
+    if (!b) return;
+    (void)hipFree(b->dmem);
+    delete[] b->fallback;
+    delete b;
 }
 
 const char *sprintz_strerror(spz_status s) {

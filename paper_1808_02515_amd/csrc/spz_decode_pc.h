@@ -74,13 +74,6 @@ __device__ __forceinline__ uint32_t lds_bits32(const uint32_t *w, uint32_t p) {
     return __builtin_amdgcn_alignbit(q[1], q[0], p);
 }
 
-struct PcSeg {
-    uint32_t ra, ext, nrec, nblk;   // container span (relative to the workgroup's), records, blocks
-    uint32_t r, cursor, rle_rem;    // next record, its payload byte, run blocks pending
-    uint32_t hbase, pbase;          // staged windows (segment byte offsets, 16-aligned)
-    uint32_t ok, tail, pad;
-};
-
 template <int W, int D, int CB, int NP, int NC> struct PcGeom {
     static constexpr uint32_t HB = W == 8 ? 3 : 4;
     static constexpr uint32_t WB = W / 8;
@@ -103,10 +96,62 @@ template <int W, int D, int CB, int NP, int NC> struct PcGeom {
     static constexpr uint32_t UPL = CB * 8 * WB / 16;              // 16-byte output units per lane
 };
 
-template <int W, bool FIRE, int D, int NP, int NC>
-__global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__restrict__ src, Geom g,
-                                                            typename Elem<W>::T *__restrict__ dst,
-                                                            int32_t *__restrict__ status) {
+// Per-segment decoding state in LDS. src and dst are the segment's first
+// container byte and first output row; everything a chunk needs is here, so
+// one workgroup can decode segments of different containers.
+struct PcSeg {
+    uint32_t r, cursor, rle_rem, nrec;   // parse: next record, its payload byte, run blocks pending, records
+    uint32_t nrow, hbase, pbase, ok;     // rows in whole blocks (x8), staged windows (16-aligned), usable
+    const uint8_t *src;                  // segment's first container byte
+    uint32_t ext, tail;                  // segment bytes, tail rows
+    uint8_t *dst;                        // segment's first output row
+    uint32_t sh;                         // FIRE shift (learn_shift + 2)
+    int32_t acc_lo, acc_hi;              // FIRE accumulator range
+    uint32_t bad, status, pad;           // corrupt, index of the status word
+};
+
+// One container (stream) of a batch, as the batched decoder sees it.
+struct PcStream {
+    const uint8_t *src;       // container (16-byte aligned)
+    uint8_t *dst;             // output rows (16-byte aligned)
+    uint64_t data_start, data_bytes, rows;
+    uint32_t nseg, S, sh;
+    int32_t acc_lo, acc_hi;
+    uint32_t pad;
+};
+
+// Validate segment `seg` of a container and fill its state: offsets from the
+// container's table, extents checked against its data bytes, the record
+// count read from the segment itself.
+__device__ __forceinline__ void pc_seg_init(PcSeg &sg, const uint8_t *src, uint64_t data_start, uint64_t data_bytes,
+                                            uint32_t nseg, uint64_t rows, uint32_t S, uint32_t seg, uint32_t D,
+                                            uint32_t HB, uint32_t WB, uint8_t *dst) {
+    sg.src = src; sg.dst = dst; sg.ext = 0; sg.nrec = 0; sg.nrow = 0; sg.tail = 0;
+    sg.r = 0; sg.cursor = 4; sg.rle_rem = 0; sg.hbase = 0; sg.pbase = 0; sg.ok = 0; sg.bad = 0;
+    if (seg >= nseg) { sg.bad = 1; return; }
+    const uint64_t a = gld64(src + 64 + 8ull * seg), b = gld64(src + 64 + 8ull * (seg + 1));
+    const uint32_t nr = (uint32_t)min((uint64_t)S, rows - (uint64_t)seg * S);
+    sg.tail = nr & 7u;
+    sg.dst = dst + (uint64_t)seg * S * D * WB;
+    if (a <= b && b <= data_bytes && !((a | b) & 15u) && b - a >= 16 && b - a <= 0x7FFFFFF0ull) {
+        sg.src = src + data_start + a;
+        sg.ext = (uint32_t)(b - a);
+        sg.nrec = gld32(sg.src);
+        sg.ok = sg.nrec <= (nr >> 3) ? 1u : 0u;
+    }
+    if (sg.ok) {
+        sg.nrow = nr & ~7u;
+        sg.cursor = 4 + (uint32_t)(((uint64_t)sg.nrec * D * HB + 7) >> 3);
+    } else {
+        sg.bad = 1;
+    }
+    sg.pbase = sg.cursor & ~15u;
+}
+
+// Decodes the segments whose state the producers put in SEG (nchunks chunks of
+// kPcChunkBlocks blocks). Called by all threads of the workgroup.
+template <int W, bool FIRE, int D, int NP, int NC, typename Init>
+__device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int32_t *__restrict__ status) {
     constexpr int CB = kPcChunkBlocks;
     using G = PcGeom<W, D, CB, NP, NC>;
     constexpr uint32_t HB = G::HB, WB = G::WB, SPW = G::SPW, SPP = G::SPP, HU = G::HU, NU = G::NU;
@@ -127,34 +172,9 @@ __global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__r
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid >> 6, lane = tid & 63;
     const bool consumer = wave >= NP;
-    const uint32_t seg0 = blockIdx.x * SPW;
-    const uint32_t nsw = min(SPW, g.nseg - seg0);
-
-    // bounded views: offset table, this workgroup's container span, its output rows
-    const Buf tab = make_buf(src + 64, 8u * (g.nseg + 1));
-    auto tab_ld = [&](uint32_t k) -> uint64_t {
-        return (uint64_t)buf_ld32(tab, 8 * k) | ((uint64_t)buf_ld32(tab, 8 * k + 4) << 32);
-    };
-    // every offset-table entry this workgroup needs, in one round trip
     const uint32_t ps0 = (consumer ? 0u : wave) * SPP;   // a producer's first segment
-    const uint32_t my_s = ps0 + lane;
-    const bool my_seg = !consumer && lane < SPP && my_s < nsw;
-    uint64_t my_a = 0, my_b = 0;
-    if (my_seg) { my_a = tab_ld(seg0 + my_s); my_b = tab_ld(seg0 + my_s + 1); }
-    const uint64_t a_wg = uniform64(tab_ld(seg0));
-    const uint64_t b_wg = uniform64(tab_ld(seg0 + nsw));
-    const bool wg_ok = a_wg <= b_wg && b_wg <= g.data_bytes && b_wg - a_wg <= 0x7FFFFFF0ull;
-    const Buf in = make_buf(src + g.data_start + (wg_ok ? a_wg : 0), wg_ok ? (uint32_t)(b_wg - a_wg) : 0u);
-    const uint64_t wrow0 = (uint64_t)seg0 * g.S;
-    const uint64_t wrows = min((uint64_t)nsw * g.S, g.rows - wrow0);
-    const Buf out = make_buf(reinterpret_cast<uint8_t *>(dst) + wrow0 * D * WB, (uint32_t)(wrows * D * WB));
-    auto seg_blocks = [&](uint32_t s) -> uint32_t {
-        return s < nsw ? (uint32_t)min((uint64_t)g.S, g.rows - (uint64_t)(seg0 + s) * g.S) >> 3 : 0u;
-    };
-    const uint32_t nchunks = ((g.S >> 3) + CB - 1) / CB;
-    uint32_t bad = 0;
 
-    // ---- producer: segment setup and the first chunk's windows ---------------
+    // ---- producers: segment state and the first chunk's windows --------------
     u32x4 reg[G::SPASS];
     auto stage_issue = [&]() {
 #pragma unroll
@@ -164,7 +184,9 @@ __global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__r
             if (u < G::SUNITS) {
                 const uint32_t s = ps0 + u / NU, k = u % NU;
                 const PcSeg &sg = SEG[s];
-                if (sg.ok) v = buf_ld128(in, sg.ra + (k < HU ? sg.hbase + 16 * k : sg.pbase + 16 * (k - HU)));
+                const uint32_t off = k < HU ? sg.hbase + 16 * k : sg.pbase + 16 * (k - HU);
+                // only whole 16-byte units inside the segment (its extent is a multiple of 16)
+                if (sg.ok && off + 16 <= sg.ext) v = gld128(sg.src + off);
             }
             reg[t] = v;
         }
@@ -177,33 +199,7 @@ __global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__r
         }
     };
     if (!consumer) {
-        if (lane < SPP) {
-            const uint32_t s = my_s;
-            PcSeg sg;
-            sg.ra = 0; sg.ext = 0; sg.nrec = 0; sg.nblk = 0; sg.r = 0; sg.cursor = 4; sg.rle_rem = 0;
-            sg.ok = 0; sg.tail = 0; sg.pad = 0;
-            if (my_seg) {
-                const uint32_t seg = seg0 + s;
-                const uint64_t a = my_a, b = my_b;
-                const uint32_t nr = (uint32_t)min((uint64_t)g.S, g.rows - (uint64_t)seg * g.S);
-                sg.tail = nr & 7u;
-                if (wg_ok && a_wg <= a && a <= b && b <= b_wg && !((a | b) & 15u) && b - a >= 16) {
-                    sg.ra = (uint32_t)(a - a_wg);
-                    sg.ext = (uint32_t)(b - a);
-                    sg.nrec = buf_ld32(in, sg.ra);
-                    sg.ok = sg.nrec <= (nr >> 3) ? 1u : 0u;
-                }
-                if (sg.ok) {
-                    sg.nblk = nr >> 3;
-                    sg.cursor = 4 + (uint32_t)(((uint64_t)sg.nrec * D * HB + 7) >> 3);
-                } else {
-                    bad = 1;
-                }
-            }
-            sg.hbase = 0;
-            sg.pbase = sg.cursor & ~15u;
-            SEG[s] = sg;
-        }
+        if (lane < SPP) init(SEG[ps0 + lane], ps0 + lane);
         wave_sync();
         stage_issue();
         stage_commit();
@@ -215,6 +211,13 @@ __global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__r
     const uint32_t cs = chain / D, cj = chain % D;
     uint32_t x = 0;
     int32_t delta = 0, acc = 0;
+    uint32_t c_sh = 0, c_nb = 0;
+    int32_t c_lo = 0, c_hi = 0;
+    uint8_t *c_dst = nullptr;
+    if (consumer) {
+        const PcSeg &q = SEG[cs];
+        c_sh = q.sh; c_lo = q.acc_lo; c_hi = q.acc_hi; c_dst = q.dst; c_nb = q.nrow >> 3;
+    }
 
     for (uint32_t t = 0; t <= nchunks; ++t) {
         if (!consumer && t < nchunks) {
@@ -226,8 +229,9 @@ __global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__r
                 const uint32_t sl = pr / CB, k = pr % CB;
                 const uint32_t s = ps0 + min(sl, SPP - 1);
                 const bool here = pr < G::PAIRS;
-                const PcSeg sg = SEG[s];
-                const uint32_t bic = c * CB < sg.nblk ? min((uint32_t)CB, sg.nblk - c * CB) : 0u;
+                const PcSeg sg = SEG[s];   // one read of the chunk's state
+                const uint32_t nbk = sg.nrow >> 3;
+                const uint32_t bic = c * CB < nbk ? min((uint32_t)CB, nbk - c * CB) : 0u;
                 const uint32_t rr = sg.r + k;
                 const bool valid = here && sg.ok && rr < sg.nrec;
                 // header codes of record rr (D * HB <= 64 bits)
@@ -251,7 +255,7 @@ __global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__r
                 const uint32_t *pw = hw + HU * 4;
                 const uint32_t cnt = lds_bits32(pw, 8 * pb) & 0xFFFFu;
                 const uint32_t nb = !valid ? 0u : zero ? cnt : 1u;
-                if (valid && zero && cnt == 0) bad = 1;
+                const bool badk = valid && zero && cnt == 0;
                 const uint32_t start = sg.rle_rem + pc_incl<CB>(nb, k) - nb;     // first block it covers
                 const bool used = valid && start < bic;
                 if (here) BM[s * CB + k] = kPcZero;
@@ -268,15 +272,17 @@ __global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__r
                 const uint32_t n_used = pc_total<CB>(used ? 1u : 0u);
                 const uint32_t adv = pc_total<CB>(used ? size : 0u);
                 const uint32_t cov = sg.rle_rem + pc_total<CB>(used ? nb : 0u);
+                const uint32_t nbad = pc_total<CB>(badk ? 1u : 0u);
+                const uint32_t r1 = sg.r + n_used, cur1 = sg.cursor + adv;
+                wave_sync();
                 if (here && k == 0) {
-                    PcSeg ns = sg;
-                    if (bic > 0 && cov < bic) bad = 1;
-                    ns.r = sg.r + n_used;
-                    ns.cursor = sg.cursor + adv;
+                    PcSeg &ns = SEG[s];
+                    if (nbad > 0 || (bic > 0 && cov < bic)) ns.bad = 1;
+                    ns.r = r1;
+                    ns.cursor = cur1;
                     ns.rle_rem = cov > bic ? cov - bic : 0u;
-                    ns.hbase = (4 + ((ns.r * D * HB) >> 3)) & ~15u;
-                    ns.pbase = ns.cursor & ~15u;
-                    SEG[s] = ns;
+                    ns.hbase = (4 + ((r1 * D * HB) >> 3)) & ~15u;
+                    ns.pbase = cur1 & ~15u;
                 }
             }
             wave_sync();
@@ -359,7 +365,8 @@ __global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__r
             // ---- recurrence: lane = column chain ------------------------------
             const uint8_t *const zc = zb + (c & 1) * G::CHAINS * ZSTR + chain * ZSTR;
             const uint32_t obase = cs * OSEG + cj * WB;
-            const uint32_t sh = g.sh;
+            const uint32_t sh = c_sh;
+            const int32_t acc_lo = c_lo, acc_hi = c_hi;
             // the whole chunk's errors first: one LDS wait per chunk
             uint32_t evs[CB][4];
 #pragma unroll
@@ -396,14 +403,13 @@ __global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__r
                     if (WB == 1) outb[o] = (uint8_t)x;
                     else *reinterpret_cast<uint16_t *>(outb + o) = (uint16_t)x;
                 }
-                if (FIRE) acc = min(max(acc + grad, g.acc_lo), g.acc_hi);
+                if (FIRE) acc = min(max(acc + grad, acc_lo), acc_hi);
             }
             wave_sync();
             // ---- output: each segment's rows of this chunk ---------------------
-            const uint32_t nb = seg_blocks(cs);
-            const uint32_t bic = c * CB < nb ? min((uint32_t)CB, nb - c * CB) : 0u;
+            const uint32_t bic = c * CB < c_nb ? min((uint32_t)CB, c_nb - c * CB) : 0u;
             const uint32_t valid = bic * 8 * D * WB;
-            const uint32_t gbase = (cs * g.S + c * CB * 8) * D * WB;
+            uint8_t *const gp = c_dst + (size_t)c * CB * 8 * D * WB;
 #pragma unroll
             for (uint32_t u = 0; u < G::UPL; ++u) {
                 const uint32_t lo = 16 * (cj + u * D);
@@ -415,11 +421,11 @@ __global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__r
                         const uint32_t *p = reinterpret_cast<const uint32_t *>(outb + cs * OSEG + lo);
                         v.x = p[0]; v.y = p[1]; v.z = p[2]; v.w = p[3];
                     }
-                    buf_st128(out, gbase + lo, v);
+                    gst128(gp + lo, v);
                 } else if (lo + 8 == valid) {
                     const uint32_t *p = reinterpret_cast<const uint32_t *>(outb + cs * OSEG + lo);
-                    __builtin_amdgcn_raw_buffer_store_b32(p[0], out.r, gbase + lo, 0, 0);
-                    __builtin_amdgcn_raw_buffer_store_b32(p[1], out.r, gbase + lo + 4, 0, 0);
+                    gst32(gp + lo, p[0]);
+                    gst32(gp + lo + 4, p[1]);
                 }
             }
         }
@@ -429,18 +435,76 @@ __global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__r
     // ---- producers: final checks and raw tail rows (a stream's last segment) ----
     if (!consumer) {
         for (uint32_t s = ps0; s < ps0 + SPP; ++s) {
-            const PcSeg sg = SEG[s];
+            PcSeg &sg = SEG[s];
             const uint32_t tb = sg.tail * D * WB;
-            if (!sg.ok) continue;
-            if (sg.r != sg.nrec || sg.rle_rem != 0 || sg.cursor + tb > sg.ext) {
-                bad = 1;
-                continue;
+            if (sg.ok && (sg.r != sg.nrec || sg.rle_rem != 0 || sg.cursor + tb > sg.ext)) {
+                if (lane == 0) sg.bad = 1;
+            } else if (sg.ok) {
+                uint8_t *const tp = sg.dst + (size_t)sg.nrow * D * WB;
+                for (uint32_t q = lane; q < tb; q += 64) gst8(tp + q, gld8(sg.src + sg.cursor + q));
             }
-            const uint32_t ob = (s * g.S + sg.nblk * 8) * D * WB;
-            for (uint32_t q = lane; q < tb; q += 64) buf_st8(out, ob + q, buf_ld8(in, sg.ra + sg.cursor + q));
         }
+        wave_sync();
+        if (lane < SPP && SEG[ps0 + lane].bad && status) atomicOr(status + SEG[ps0 + lane].status, 1);
     }
-    if (bad && status) atomicOr(status, 1);
+}
+
+// One container: workgroup b decodes segments [b * SPW, b * SPW + SPW).
+template <int W, bool FIRE, int D, int NP, int NC>
+__global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__restrict__ src, Geom g,
+                                                            typename Elem<W>::T *__restrict__ dst,
+                                                            int32_t *__restrict__ status) {
+    using G = PcGeom<W, D, kPcChunkBlocks, NP, NC>;
+    const uint32_t seg0 = blockIdx.x * G::SPW;
+    auto init = [&](PcSeg &sg, uint32_t s) {
+        pc_seg_init(sg, src, g.data_start, g.data_bytes, g.nseg, g.rows, g.S, seg0 + s, D, G::HB, G::WB,
+                    reinterpret_cast<uint8_t *>(dst));
+        if (seg0 + s >= g.nseg) sg.bad = 0;   // past the last segment: nothing to do
+        sg.sh = g.sh; sg.acc_lo = g.acc_lo; sg.acc_hi = g.acc_hi; sg.status = 0;
+    };
+    const uint32_t nchunks = ((g.S >> 3) + kPcChunkBlocks - 1) / kPcChunkBlocks;
+    pc_decode_group<W, FIRE, D, NP, NC>(nchunks, init, status);
+}
+
+// Many containers: a persistent grid pulls groups of SPW work-list entries
+// (stream << 32 | segment, ~0 = empty) from a device queue; the segments of a
+// group share one seg_rows (group_s). Status bits go to status[stream].
+template <int W, bool FIRE, int D, int NP, int NC>
+__global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc_batch(const PcStream *__restrict__ streams,
+                                                                  const uint64_t *__restrict__ entries,
+                                                                  const uint32_t *__restrict__ group_s, uint32_t ngroups,
+                                                                  uint32_t *__restrict__ queue,
+                                                                  int32_t *__restrict__ status) {
+    using G = PcGeom<W, D, kPcChunkBlocks, NP, NC>;
+    __shared__ uint32_t grp_sh;
+    for (;;) {
+        if (threadIdx.x == 0) grp_sh = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t grp = grp_sh;
+        __syncthreads();
+        if (grp >= ngroups) break;
+        auto init = [&](PcSeg &sg, uint32_t s) {
+            const uint64_t e = entries[(uint64_t)grp * G::SPW + s];
+            const uint32_t si = (uint32_t)(e >> 32);
+            if (e == ~0ull) {
+                sg.ok = 0; sg.bad = 0; sg.nrow = 0; sg.tail = 0; sg.ext = 0; sg.nrec = 0;
+                sg.r = 0; sg.cursor = 4; sg.rle_rem = 0; sg.hbase = 0; sg.pbase = 0; sg.status = 0;
+                sg.src = nullptr; sg.dst = nullptr; sg.sh = 0; sg.acc_lo = 0; sg.acc_hi = 0;
+                return;
+            }
+            const PcStream st = streams[si];
+            pc_seg_init(sg, st.src, st.data_start, st.data_bytes, st.nseg, st.rows, st.S, (uint32_t)e, D, G::HB,
+                        G::WB, st.dst);
+            sg.sh = st.sh; sg.acc_lo = st.acc_lo; sg.acc_hi = st.acc_hi; sg.status = si;
+        };
+        const uint32_t nchunks = ((group_s[grp] >> 3) + kPcChunkBlocks - 1) / kPcChunkBlocks;
+        pc_decode_group<W, FIRE, D, NP, NC>(nchunks, init, status);
+        __syncthreads();
+    }
+}
+
+__global__ void k_zero_u32(uint32_t *p, uint32_t n) {
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
 }  // namespace spz

@@ -127,6 +127,18 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Global-memory accessors for pointers the compiler cannot trace to a kernel
+// argument (for instance pointers kept in LDS): without the address space they
+// become flat accesses, which also count against the LDS wait counter.
+#define SPZ_GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ u32x4 gld128(const uint8_t *p) { return *(const SPZ_GLOBAL u32x4 *)p; }
+__device__ __forceinline__ void gst128(uint8_t *p, u32x4 v) { *(SPZ_GLOBAL u32x4 *)p = v; }
+__device__ __forceinline__ void gst32(uint8_t *p, uint32_t v) { *(SPZ_GLOBAL uint32_t *)p = v; }
+__device__ __forceinline__ uint32_t gld8(const uint8_t *p) { return *(const SPZ_GLOBAL uint8_t *)p; }
+__device__ __forceinline__ uint32_t gld32(const uint8_t *p) { return *(const SPZ_GLOBAL uint32_t *)p; }
+__device__ __forceinline__ uint64_t gld64(const uint8_t *p) { return *(const SPZ_GLOBAL uint64_t *)p; }
+__device__ __forceinline__ void gst8(uint8_t *p, uint32_t v) { *(SPZ_GLOBAL uint8_t *)p = (uint8_t)v; }
+
 // Make a value the compiler cannot prove uniform usable as a scalar operand.
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {

@@ -232,45 +232,59 @@ __global__ __launch_bounds__(1024) void k_scan_sizes(const uint32_t *__restrict_
                                                      uint32_t dtype, uint32_t forecaster, uint32_t learn_shift,
                                                      uint8_t *__restrict__ dst, uint64_t *__restrict__ out_size,
                                                      int32_t *__restrict__ status) {
-    __shared__ uint64_t part[1024];
-    const uint32_t t = threadIdx.x;
+    // Exclusive scan of the segment byte sizes into the offset table, 1024
+    // entries per step (coalesced loads, wavefront shuffle scans, one LDS
+    // exchange of the 16 wavefront totals), then the container header.
+    __shared__ uint64_t wsum[16];
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const uint32_t n = g.nseg;
-    const uint32_t per = (n + 1023) / 1024;
-    const uint32_t lo = min(t * per, n), hi = min(lo + per, n);
-    uint64_t s = 0;
-    for (uint32_t k = lo; k < hi; ++k) s += seg_info[2 * k];
-    part[t] = s;
-    __syncthreads();
-    for (uint32_t d = 1; d < 1024; d <<= 1) {  // Hillis-Steele inclusive scan
-        uint64_t v = t >= d ? part[t - d] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    uint64_t off = part[t] - s;
     uint64_t *tab = reinterpret_cast<uint64_t *>(dst + 64);
-    for (uint32_t k = lo; k < hi; ++k) {
-        tab[k] = off;
-        off += seg_info[2 * k];
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < n; base += 1024) {
+        const uint32_t k = base + t;
+        const uint32_t v = k < n ? seg_info[2 * k] : 0u;
+        uint64_t incl = v;
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint64_t o = (uint64_t)__shfl_up((unsigned long long)incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        uint64_t before = carry, total = carry;
+        for (uint32_t q = 0; q < 16; ++q) {
+            const uint64_t ws = wsum[q];
+            if (q < wv) before += ws;
+            total += ws;
+        }
+        if (k < n) tab[k] = before + incl - v;
+        carry = total;
+        __syncthreads();
     }
-    const uint64_t total = part[1023];
+    if (t == 0) tab[n] = carry;
+    if (t < 16) {
+        // 64-byte header as 16 dwords (reading R18: the container layout)
+        uint32_t word = 0;
+        switch (t) {
+            case 0: word = 0x315A5053u; break;                                            // "SPZ1"
+            case 1: word = 1u | (w << 16) | (dtype << 24); break;                          // version, w, dtype
+            case 2: word = forecaster | (learn_shift << 8) | (g.G << 16); break;           // entropy 0
+            case 3: word = g.D; break;
+            case 4: word = (uint32_t)g.rows; break;
+            case 5: word = (uint32_t)(g.rows >> 32); break;
+            case 6: word = g.S; break;
+            case 7: word = n; break;
+            case 8: word = (uint32_t)carry; break;
+            case 9: word = (uint32_t)(carry >> 32); break;
+            default: word = 0; break;
+        }
+        reinterpret_cast<uint32_t *>(dst)[t] = word;
+    }
+    // zero padding between the offset table and the data
+    const uint64_t pad0 = 64 + 8ull * (n + 1);
+    if (t < g.data_start - pad0) dst[pad0 + t] = 0;
     if (t == 0) {
-        tab[n] = total;
-        uint8_t h[64];
-        for (int k = 0; k < 64; ++k) h[k] = 0;
-        h[0] = 'S'; h[1] = 'P'; h[2] = 'Z'; h[3] = '1';
-        h[4] = 1; h[5] = 0;
-        h[6] = (uint8_t)w; h[7] = (uint8_t)dtype; h[8] = (uint8_t)forecaster; h[9] = (uint8_t)learn_shift;
-        h[10] = (uint8_t)g.G; h[11] = 0;
-        for (int k = 0; k < 4; ++k) h[12 + k] = (uint8_t)(g.D >> (8 * k));
-        for (int k = 0; k < 8; ++k) h[16 + k] = (uint8_t)(g.rows >> (8 * k));
-        for (int k = 0; k < 4; ++k) h[24 + k] = (uint8_t)(g.S >> (8 * k));
-        for (int k = 0; k < 4; ++k) h[28 + k] = (uint8_t)(n >> (8 * k));
-        for (int k = 0; k < 8; ++k) h[32 + k] = (uint8_t)(total >> (8 * k));
-        for (int k = 0; k < 64; ++k) dst[k] = h[k];
-        for (uint64_t k = 64 + 8ull * (n + 1); k < g.data_start; ++k) dst[k] = 0;
-        *out_size = g.data_start + total;
-        if (g.data_start + total > g.cap && status) atomicOr(status, 2);
+        *out_size = g.data_start + carry;
+        if (g.data_start + carry > g.cap && status) atomicOr(status, 2);
     }
 }
 
