@@ -68,6 +68,18 @@ template <int N> __device__ __forceinline__ uint32_t pc_total(uint32_t v) {
     return v;
 }
 
+// Unzigzag of two 16-bit (four 8-bit) fields of a dword at once.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t unzigzag16x2(uint32_t zz) {
+    const u16x2 v = __builtin_bit_cast(u16x2, zz);
+    const u16x2 one = {1, 1}, zero = {0, 0};
+    return __builtin_bit_cast(uint32_t, (u16x2)((v >> one) ^ (zero - (v & one))));
+}
+__device__ __forceinline__ uint32_t unzigzag8x4(uint32_t zz) {
+    const uint32_t low = zz & 0x01010101u;
+    return ((zz >> 1) & 0x7F7F7F7Fu) ^ ((low << 8) - low);
+}
+
 // The 32 bits starting at bit p of an LDS word array (two aligned reads).
 __device__ __forceinline__ uint32_t lds_bits32(const uint32_t *w, uint32_t p) {
     const uint32_t *q = w + (p >> 5);
@@ -157,14 +169,23 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
     constexpr uint32_t HB = G::HB, WB = G::WB, SPW = G::SPW, SPP = G::SPP, HU = G::HU, NU = G::NU;
     constexpr uint32_t ZSTR = G::ZSTR, OSEG = G::OSEG;
     constexpr bool ROW = D * W > 32;   // row-major payloads (reading R13)
-    static_assert(SPP * NP == SPW && CB <= 16, "geometry");
+    static_assert(SPP * NP == SPW && CB <= 16 && 64 % SPP == 0, "geometry");
 
-    __shared__ u32x4 STG[SPW * NU];                   // [segment][header window | payload window]
-    __shared__ u32x4 ZB4[2 * G::CHAINS * ZSTR / 16];   // [buffer][chain] errors of a chunk
-    __shared__ uint32_t OUTW[SPW * OSEG / 4];         // [segment] output rows of a chunk
-    __shared__ u32x4 REC[SPW * CB];                   // [segment][candidate]: codes lo, hi, payload bit, bits per row
-    __shared__ uint32_t BM[SPW * CB];                 // [segment][block]: candidate or kPcZero
-    __shared__ PcSeg SEG[SPW];
+    // One LDS arena, staging windows first: field addresses then need no base.
+    constexpr uint32_t O_ZB = SPW * NU * 16;                       // [segment][header window | payload window]
+    constexpr uint32_t O_OUT = O_ZB + 2 * G::CHAINS * ZSTR;        // [buffer][chain] errors of a chunk
+    constexpr uint32_t O_REC = (O_OUT + SPW * OSEG + 15) & ~15u;   // [segment] output rows of a chunk
+    constexpr uint32_t O_BM = O_REC + SPW * CB * 16;               // [segment][candidate]: codes lo, hi, payload bit, bits per row
+    constexpr uint32_t O_SEG = (O_BM + SPW * CB * 4 + 15) & ~15u;  // [segment][block]: candidate or kPcZero
+    constexpr uint32_t O_END = O_SEG + SPW * (uint32_t)sizeof(PcSeg);
+    __shared__ u32x4 ARENA[O_END / 16];
+    u32x4 *const STG = ARENA;
+    u32x4 *const ZB4 = reinterpret_cast<u32x4 *>(reinterpret_cast<uint8_t *>(ARENA) + O_ZB);
+    uint32_t *const OUTW = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(ARENA) + O_OUT);
+    u32x4 *const REC = reinterpret_cast<u32x4 *>(reinterpret_cast<uint8_t *>(ARENA) + O_REC);
+    uint32_t *const BM = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(ARENA) + O_BM);
+    PcSeg *const SEG = reinterpret_cast<PcSeg *>(reinterpret_cast<uint8_t *>(ARENA) + O_SEG);
+    static_assert(O_END % 16 == 0 && sizeof(PcSeg) % 16 == 0, "arena layout");
     const uint32_t *const stgw = reinterpret_cast<const uint32_t *>(STG);
     uint8_t *const zb = reinterpret_cast<uint8_t *>(ZB4);
     uint8_t *const outb = reinterpret_cast<uint8_t *>(OUTW);
@@ -175,27 +196,31 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
     const uint32_t ps0 = (consumer ? 0u : wave) * SPP;   // a producer's first segment
 
     // ---- producers: segment state and the first chunk's windows --------------
-    u32x4 reg[G::SPASS];
+    // staging: each lane moves units of one segment (64 / SPP lanes per segment),
+    // so it reads that segment's state once per chunk
+    constexpr uint32_t LPS = 64 / SPP;                  // lanes per segment
+    constexpr uint32_t SP2 = (NU + LPS - 1) / LPS;      // units per lane
+    const uint32_t st_s = ps0 + lane / LPS, st_k = lane % LPS;
+    u32x4 reg[SP2];
     auto stage_issue = [&]() {
+        const PcSeg &sg = SEG[st_s];
+        const uint8_t *const src = sg.src;
+        const uint32_t ext = sg.ok ? sg.ext : 0u, hbase = sg.hbase, pbase = sg.pbase;
 #pragma unroll
-        for (uint32_t t = 0; t < G::SPASS; ++t) {
-            const uint32_t u = lane + 64 * t;
+        for (uint32_t t = 0; t < SP2; ++t) {
+            const uint32_t k = st_k + LPS * t;
+            const uint32_t off = k < HU ? hbase + 16 * k : pbase + 16 * (k - HU);
             u32x4 v = {0u, 0u, 0u, 0u};
-            if (u < G::SUNITS) {
-                const uint32_t s = ps0 + u / NU, k = u % NU;
-                const PcSeg &sg = SEG[s];
-                const uint32_t off = k < HU ? sg.hbase + 16 * k : sg.pbase + 16 * (k - HU);
-                // only whole 16-byte units inside the segment (its extent is a multiple of 16)
-                if (sg.ok && off + 16 <= sg.ext) v = gld128(sg.src + off);
-            }
+            // only whole 16-byte units inside the segment (its extent is a multiple of 16)
+            if (k < NU && off + 16 <= ext) v = gld128(src + off);
             reg[t] = v;
         }
     };
     auto stage_commit = [&]() {
 #pragma unroll
-        for (uint32_t t = 0; t < G::SPASS; ++t) {
-            const uint32_t u = lane + 64 * t;
-            if (u < G::SUNITS) STG[ps0 * NU + u] = reg[t];
+        for (uint32_t t = 0; t < SP2; ++t) {
+            const uint32_t k = st_k + LPS * t;
+            if (k < NU) STG[st_s * NU + k] = reg[t];
         }
     };
     if (!consumer) {
@@ -246,7 +271,7 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
                     const uint32_t code = bp + HB <= 32 ? __builtin_amdgcn_ubfe(cw_lo, bp, HB)
                                           : bp >= 32    ? __builtin_amdgcn_ubfe(cw_hi, bp - 32, HB)
                                                         : __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(cw_hi, cw_lo, bp), 0, HB);
-                    total += code == (uint32_t)W - 1 ? (uint32_t)W : code;
+                    total += code + ((code + 1) >> HB);   // code w-1 stands for width w
                 }
                 const bool zero = total == 0;
                 const uint32_t size = !valid ? 0u : zero ? 2u : (ROW ? 8 * ((total + 7) >> 3) : total);
@@ -320,7 +345,7 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
                                       : bp + HB <= 32 ? __builtin_amdgcn_ubfe(rec.x, bp, HB)
                                       : bp >= 32      ? __builtin_amdgcn_ubfe(rec.y, bp - 32, HB)
                                                       : __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(rec.y, rec.x, bp), 0, HB);
-                const uint32_t width = code == (uint32_t)W - 1 ? (uint32_t)W : code;
+                const uint32_t width = code + ((code + 1) >> HB);   // code w-1 stands for width w
                 const uint32_t off = pc_incl<D>(width, j) - width;
                 const uint32_t p0 = nz ? rec.z + (ROW ? off : 8 * off) : 0u;
                 const uint32_t step = !nz ? 0u : ROW ? rec.w : width;
@@ -338,22 +363,24 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
             for (uint32_t ip = 0; ip < IP; ++ip) {
                 const uint32_t it = lane + 64 * ip;
                 const uint32_t j = it % D, b = (it / D) % CB, s = ps0 + min(it / (D * CB), SPP - 1);
-                int32_t e[8];
+                uint32_t z[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) e[i] = unzigzag(__builtin_amdgcn_ubfe(fw[ip][i][0], 0, wd[ip]));
+                for (int i = 0; i < 8; ++i) z[i] = __builtin_amdgcn_ubfe(fw[ip][i][0], 0, wd[ip]);
                 if (it < G::ITEMS) {
                     uint8_t *zp = zbuf + (s * D + j) * ZSTR + b * 8 * WB;
+                    // zigzag fields packed 2 (or 4) per dword, then unzigzagged lane-wise:
+                    // e = (z >> 1) ^ -(z & 1) in every 16-bit (8-bit) lane
                     if (WB == 2) {
                         u32x4 v;
-                        v.x = (e[0] & 0xFFFFu) | ((uint32_t)e[1] << 16);
-                        v.y = (e[2] & 0xFFFFu) | ((uint32_t)e[3] << 16);
-                        v.z = (e[4] & 0xFFFFu) | ((uint32_t)e[5] << 16);
-                        v.w = (e[6] & 0xFFFFu) | ((uint32_t)e[7] << 16);
+                        v.x = unzigzag16x2(z[0] | (z[1] << 16));
+                        v.y = unzigzag16x2(z[2] | (z[3] << 16));
+                        v.z = unzigzag16x2(z[4] | (z[5] << 16));
+                        v.w = unzigzag16x2(z[6] | (z[7] << 16));
                         *reinterpret_cast<u32x4 *>(zp) = v;
                     } else {
                         uint2 v;
-                        v.x = (e[0] & 0xFFu) | ((e[1] & 0xFFu) << 8) | ((e[2] & 0xFFu) << 16) | ((uint32_t)e[3] << 24);
-                        v.y = (e[4] & 0xFFu) | ((e[5] & 0xFFu) << 8) | ((e[6] & 0xFFu) << 16) | ((uint32_t)e[7] << 24);
+                        v.x = unzigzag8x4(z[0] | (z[1] << 8) | (z[2] << 16) | (z[3] << 24));
+                        v.y = unzigzag8x4(z[4] | (z[5] << 8) | (z[6] << 16) | (z[7] << 24));
                         *reinterpret_cast<uint2 *>(zp) = v;
                     }
                 }
