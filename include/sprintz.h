@@ -150,6 +150,19 @@ typedef struct spz_batch spz_batch;
  * keeps the buffers alive and unchanged in size while the plan is used. */
 spz_status sprintz_batch_create(const spz_batch_item *items, const spz_info *infos, uint32_t n, spz_batch **out);
 
+/* Device bytes of the plan tables for these items (0 if an item is invalid). */
+size_t sprintz_batch_workspace_size(const spz_batch_item *items, const spz_info *infos, uint32_t n);
+
+/* As sprintz_batch_create, but the tables go to the caller's device workspace
+ * d_ws (16-byte aligned, ws_size >= sprintz_batch_workspace_size) with an
+ * asynchronous copy on `stream`, so that plans can be made while other work
+ * runs (the serving loop does this). Allocates no device memory; the plan
+ * keeps the host copy of the tables until sprintz_batch_destroy, which the
+ * caller calls once that copy and every use of the plan have completed.
+ * SPZ_ENOSPC if ws_size is too small. */
+spz_status sprintz_batch_create_in(const spz_batch_item *items, const spz_info *infos, uint32_t n, void *d_ws,
+                                   size_t ws_size, hipStream_t stream, spz_batch **out);
+
 /* Enqueue the decoding of every item of the plan on `stream`: a tiny kernel
  * resets the per-class queues, then one launch per nonempty class, then the
  * fallback streams. d_status: n int32 device words (zero on entry, or NULL);

@@ -63,6 +63,11 @@ _SIGNATURES = {
                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
     "sprintz_batch_create": (ctypes.c_int, [ctypes.POINTER(spz_batch_item), ctypes.POINTER(spz_info),
                                             ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
+    "sprintz_batch_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(spz_batch_item), ctypes.POINTER(spz_info),
+                                                       ctypes.c_uint32]),
+    "sprintz_batch_create_in": (ctypes.c_int, [ctypes.POINTER(spz_batch_item), ctypes.POINTER(spz_info),
+                                               ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                               ctypes.POINTER(ctypes.c_void_p)]),
     "sprintz_batch_decompress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sprintz_batch_destroy": (None, [ctypes.c_void_p]),
     "sprintz_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -142,6 +147,24 @@ def sprintz_batch_create(items, infos) -> int:
     rc = load().sprintz_batch_create(arr_i, arr_f, n, ctypes.byref(h))
     if rc != SPZ_OK:
         raise SprintzError(rc, "sprintz_batch_create")
+    return h.value
+
+
+def sprintz_batch_workspace_size(items, infos) -> int:
+    n = len(items)
+    arr_i = (spz_batch_item * max(n, 1))(*items)
+    arr_f = (spz_info * max(n, 1))(*infos)
+    return int(load().sprintz_batch_workspace_size(arr_i, arr_f, n))
+
+
+def sprintz_batch_create_in(items, infos, d_ws: int, ws_size: int, stream: int) -> int:
+    n = len(items)
+    arr_i = (spz_batch_item * max(n, 1))(*items)
+    arr_f = (spz_info * max(n, 1))(*infos)
+    h = ctypes.c_void_p()
+    rc = load().sprintz_batch_create_in(arr_i, arr_f, n, d_ws, ws_size, stream, ctypes.byref(h))
+    if rc != SPZ_OK:
+        raise SprintzError(rc, "sprintz_batch_create_in")
     return h.value
 
 

@@ -9,6 +9,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -320,22 +322,35 @@ hipError_t launch_batch_class(const spz::PcStream *streams, const uint64_t *entr
 
 template <int W, bool FIRE, int D>
 uint32_t batch_grid_cap() {
-    // resident workgroups of this kernel on the current device (1 if the query fails)
+    // resident workgroups of this kernel on the current device (1 if the query
+    // fails), cached per device
+    static std::mutex mu;
+    static std::map<int, uint32_t> cache;
     int per_cu = 0, dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(dev);
+        if (it != cache.end()) return it->second;
+    }
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &per_cu, (const void *)spz::k_decode_pc_batch<W, FIRE, D, spz::kPcProducers, spz::kPcConsumers>,
             64 * (spz::kPcProducers + spz::kPcConsumers), 0) != hipSuccess)
         return 1;
-    return (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)(cus > 0 ? cus : 1);
+    const uint32_t cap = (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)(cus > 0 ? cus : 1);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[dev] = cap;
+    return cap;
 }
 
 }  // namespace
 
 struct spz_batch {
     uint32_t n;
-    void *dmem;                                    // one device allocation for everything below
+    void *dmem;                                    // device tables: own allocation, or the caller's workspace
+    bool owns;                                     // dmem allocated by the library
+    std::vector<uint8_t> host;                     // host image of the tables (kept for asynchronous uploads)
     spz::PcStream *streams;
     uint64_t *entries[kClasses];
     uint32_t *group_s[kClasses];
@@ -358,18 +373,20 @@ spz_status sprintz_decompress(const void *d_src, size_t src_size, const spz_info
     return launch_decode_any(d_src, info, g, d_dst, d_status, stream) == hipSuccess ? SPZ_OK : SPZ_EHIP;
 }
 
-spz_status sprintz_batch_create(const spz_batch_item *items, const spz_info *infos, uint32_t n, spz_batch **out) {
-    if (!out || (n > 0 && (!items || !infos))) return SPZ_EINVAL;
-    *out = nullptr;
-    spz_batch *b = new (std::nothrow) spz_batch();
-    if (!b) return SPZ_ENOMEM;
+}  // extern "C"
+
+namespace {
+
+// Builds the plan's tables on the host (b->host) and the pointers into them
+// relative to device address `base` (nullptr: offsets only, for sizing).
+spz_status build_plan(const spz_batch_item *items, const spz_info *infos, uint32_t n, spz_batch *b, uint8_t *base) {
     b->n = n;
     std::vector<spz::Geom> geoms(n);
     std::vector<int> cls(n, -1);
     for (uint32_t i = 0; i < n; ++i) {
         const spz_status st =
             check_decompress(items[i].d_src, items[i].src_size, &infos[i], items[i].d_dst, items[i].dst_cap, &geoms[i]);
-        if (st != SPZ_OK) { delete b; return st; }
+        if (st != SPZ_OK) return st;
         const spz_info &in = infos[i];
         const uint32_t D = in.D;
         const bool pow2 = (D & (D - 1)) == 0 && D <= 16;
@@ -410,8 +427,8 @@ spz_status sprintz_batch_create(const spz_batch_item *items, const spz_info *inf
         while (ent[c].size() % spw) ent[c].push_back(~0ull);
         bytes += ent[c].size() * 8 + gs[c].size() * 4 + 16;
     }
-    if (hipMalloc(&b->dmem, bytes) != hipSuccess) { delete b; return SPZ_ENOMEM; }
-    std::vector<uint8_t> host(bytes, 0);
+    b->host.assign(bytes, 0);
+    std::vector<uint8_t> &host = b->host;
     size_t off = 0;
     auto carve = [&](size_t sz) { const size_t o = off; off = (off + sz + 15) & ~size_t(15); return o; };
     const size_t o_streams = carve(sizeof(spz::PcStream) * (size_t)n);
@@ -440,12 +457,6 @@ spz_status sprintz_batch_create(const spz_batch_item *items, const spz_info *inf
         if (!gs[c].empty()) memcpy(host.data() + o_gs[c], gs[c].data(), gs[c].size() * 4);
     }
     const size_t o_q = carve(sizeof(uint32_t) * kClasses);
-    if (hipMemcpy(b->dmem, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(b->dmem);
-        delete b;
-        return SPZ_EHIP;
-    }
-    uint8_t *base = (uint8_t *)b->dmem;
     b->streams = (spz::PcStream *)(base + o_streams);
     b->queues = (uint32_t *)(base + o_q);
     for (int c = 0; c < kClasses; ++c) {
@@ -464,12 +475,61 @@ spz_status sprintz_batch_create(const spz_batch_item *items, const spz_info *inf
     b->fallback = nullptr;
     if (!fb.empty()) {
         b->fallback = new (std::nothrow) spz_batch::Fallback[fb.size()];
-        if (!b->fallback) { (void)hipFree(b->dmem); delete b; return SPZ_ENOMEM; }
+        if (!b->fallback) return SPZ_ENOMEM;
         std::copy(fb.begin(), fb.end(), b->fallback);
     }
+    return SPZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sprintz_batch_workspace_size(const spz_batch_item *items, const spz_info *infos, uint32_t n) {
+    if (n > 0 && (!items || !infos)) return 0;
+    spz_batch b{};
+    if (build_plan(items, infos, n, &b, nullptr) != SPZ_OK) { delete[] b.fallback; return 0; }
+    delete[] b.fallback;
+    return b.host.size();
+}
+
+spz_status sprintz_batch_create(const spz_batch_item *items, const spz_info *infos, uint32_t n, spz_batch **out) {
+    if (!out || (n > 0 && (!items || !infos))) return SPZ_EINVAL;
+    *out = nullptr;
+    spz_batch *b = new (std::nothrow) spz_batch();
+    if (!b) return SPZ_ENOMEM;
+    spz_status st = build_plan(items, infos, n, b, nullptr);   // size first
+    if (st != SPZ_OK) { delete[] b->fallback; delete b; return st; }
+    delete[] b->fallback;
+    b->fallback = nullptr;
+    if (hipMalloc(&b->dmem, b->host.size()) != hipSuccess) { delete b; return SPZ_ENOMEM; }
+    b->owns = true;
+    st = build_plan(items, infos, n, b, (uint8_t *)b->dmem);
+    if (st == SPZ_OK && hipMemcpy(b->dmem, b->host.data(), b->host.size(), hipMemcpyHostToDevice) != hipSuccess)
+        st = SPZ_EHIP;
+    if (st != SPZ_OK) { (void)hipFree(b->dmem); delete[] b->fallback; delete b; return st; }
     *out = b;
     return SPZ_OK;
 }
+
+spz_status sprintz_batch_create_in(const spz_batch_item *items, const spz_info *infos, uint32_t n, void *d_ws,
+                                   size_t ws_size, hipStream_t stream, spz_batch **out) {
+    if (!out || (n > 0 && (!items || !infos)) || !d_ws || ((uintptr_t)d_ws & 15)) return SPZ_EINVAL;
+    *out = nullptr;
+    spz_batch *b = new (std::nothrow) spz_batch();
+    if (!b) return SPZ_ENOMEM;
+    spz_status st = build_plan(items, infos, n, b, (uint8_t *)d_ws);
+    if (st == SPZ_OK && b->host.size() > ws_size) st = SPZ_ENOSPC;
+    if (st == SPZ_OK &&
+        hipMemcpyAsync(d_ws, b->host.data(), b->host.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
+        st = SPZ_EHIP;
+    if (st != SPZ_OK) { delete[] b->fallback; delete b; return st; }
+    b->dmem = d_ws;
+    b->owns = false;
+    *out = b;
+    return SPZ_OK;
+}
+
 
 spz_status sprintz_batch_decompress(const spz_batch *b, int32_t *d_status, hipStream_t stream) {
     if (!b) return SPZ_EINVAL;
@@ -497,7 +557,7 @@ spz_status sprintz_batch_decompress(const spz_batch *b, int32_t *d_status, hipSt
 
 void sprintz_batch_destroy(spz_batch *b) {
     if (!b) return;
-    (void)hipFree(b->dmem);
+    if (b->owns) (void)hipFree(b->dmem);
     delete[] b->fallback;
     delete b;
 }
