@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: requests per second (Poisson)")
     ap.add_argument("--streams", type=int, default=10000, help="batch workload: number of streams")
+    ap.add_argument("--batch-streams", type=int, default=1000,
+                    help="stream workload: also run this many streams of the batch workload, batched vs one "
+                         "launch per stream (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -116,7 +119,7 @@ def main():
 
     spz.load()
     if args.workload == "batch":
-        run_batch(args)
+        print(json.dumps(run_batch(args)), flush=True)
         return
     if args.workload == "serve":
         run_serve(args)
@@ -231,6 +234,16 @@ def main():
         "cpu_baseline": cpu,
         "paper_context": "paper: >3 GB/s single-thread decompression on an Intel i7-4960HQ (2.6 GHz, AVX2)",
     }
+    if args.batch_streams > 0:
+        del xs, encs, ys
+        torch.cuda.empty_cache()
+        bargs = argparse.Namespace(**vars(args))
+        bargs.streams, bargs.steps, bargs.warmup, bargs.no_cpu_baseline = args.batch_streams, 5, 2, True
+        b = run_batch(bargs)
+        out["batched_vs_plain"] = {k: b[k] for k in (
+            "batch_decode_GBps", "per_stream_decode_GBps", "batched_vs_per_stream", "graph_decode_GBps",
+            "u16_fire_decode_GBps", "u16_fire_hbm_frac", "compression_ratio", "parity")}
+        out["batched_vs_plain"]["workload"] = b["config"]["workload"]
     print(json.dumps(out), flush=True)
 
 
@@ -430,7 +443,7 @@ def run_batch(args):
         "autotune": {f"{8 * k[0]}bit_D{k[1]}": v[1] for k, v in tune.items()},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def run_serve(args):
