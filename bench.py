@@ -83,9 +83,9 @@ def main():
     ap.add_argument("--seg-rows", type=int, default=1024)
     ap.add_argument("--rotate", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="stream", choices=["stream", "batch", "serve"],
+    ap.add_argument("--workload", default="stream", choices=["stream", "batch", "serve", "dsweep"],
                     help="stream: the 4,194,304 x 8 uint16 stream; batch: the many-stream batch; "
-                         "serve: the request-serving loop")
+                         "serve: the request-serving loop; dsweep: speed against D on uniform values")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: requests per second (Poisson)")
     ap.add_argument("--streams", type=int, default=10000, help="batch workload: number of streams")
@@ -123,6 +123,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "dsweep":
+        run_dsweep(args)
         return
     dev = torch.device("cuda:0")
     rows, D = 4194304, 8
@@ -444,6 +447,76 @@ def run_batch(args):
         "cpu_baseline": cpu,
     }
     return out
+
+
+def run_dsweep(args, values=100_000_000):
+    """Encode and decode speed against D on full-range uniform values (the
+    paper's speed workload, Section 5.4: every block needs the full width),
+    about 100M values per point, 8- and 16-bit, delta and FIRE, one stream per
+    call, seg_rows 1024 (2048 where 1024 * D * w/8 is not a multiple of 16)."""
+    import torch
+    import paper_1808_02515_amd as spz
+
+    res = []
+    for w in (8, 16):
+        for D in (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64):
+            rows = values // D
+            g = torch.Generator(device="cuda")
+            g.manual_seed(D * 100 + w)
+            dt = torch.int8 if w == 8 else torch.int16
+            x = torch.randint(-(1 << (w - 1)), 1 << (w - 1), (rows, D), generator=g, device="cuda",
+                              dtype=torch.int32).to(dt)
+            U = x.numel() * x.element_size()
+            for f in ("delta", "fire"):
+                S = 1024
+                while (S * D * (w // 8)) % 16:
+                    S *= 2
+                p = spz.make_params(f, S)
+                enc = spz.Encoder.create(rows, D, spz.dtype_code(x), p)
+                enc.run(x)
+                torch.cuda.synchronize()
+                csize = int(enc.out_size.item())
+                cont = enc.dst[:csize]
+                info = spz.info_of(cont)
+                y = torch.empty_like(x)
+                st = torch.zeros(1, dtype=torch.int32, device="cuda")
+                sh = torch.cuda.current_stream().cuda_stream
+                def dec():
+                    rc = spz.sprintz_decompress(cont.data_ptr(), csize, info, y.data_ptr(), U, st.data_ptr(), sh)
+                    if rc != spz.SPZ_OK:
+                        raise spz.SprintzError(rc, "sprintz_decompress")
+                dec()
+                ev = _events(6)
+                for k, (a, b) in enumerate(ev):
+                    a.record()
+                    (enc.run(x) if k % 2 == 0 else dec())
+                    b.record()
+                torch.cuda.synchronize()
+                te = min(a.elapsed_time(b) for k, (a, b) in enumerate(ev) if k % 2 == 0)
+                td = min(a.elapsed_time(b) for k, (a, b) in enumerate(ev) if k % 2 == 1)
+                ok = torch.equal(x, y) and int(st.item()) == 0 and int(enc.status.item()) == 0
+                if not ok:
+                    print(f"[bench] PARITY FAILURE dsweep w={w} D={D} {f}", file=sys.stderr, flush=True)
+                    sys.exit(1)
+                res.append({"w": w, "D": D, "forecaster": f, "seg_rows": S, "ratio": round(U / csize, 4),
+                            "decode_GBps": round(U / td * 1e-6, 2), "encode_GBps": round(U / te * 1e-6, 2)})
+                print(f"[bench] w={w} D={D:2d} {f:5s} decode {res[-1]['decode_GBps']:8.1f} GB/s "
+                      f"encode {res[-1]['encode_GBps']:8.1f} GB/s", file=sys.stderr, flush=True)
+                del enc, y, cont
+            del x
+            torch.cuda.empty_cache()
+    dec16 = [r["decode_GBps"] for r in res if r["w"] == 16 and r["forecaster"] == "fire"]
+    out = {
+        "metric": "decode GB/s and encode GB/s (uncompressed bytes), % HBM peak, batched vs plain",
+        "value": round(float(np.median(dec16)), 2), "unit": "GB/s", "n_gpus": 1, "steps": 3, "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8/u16",
+        "data": "synthetic",
+        "config": {"workload": "D sweep on uniform values (~1e8 values per point), one stream per call"},
+        "value_note": "median decode GB/s of the 16-bit FIRE points",
+        "sweep": res, "roofline": None, "cpu_baseline": None,
+        "paper_context": "paper Section 5.4: decompression speed against D on uniform values, single-threaded CPU",
+    }
+    print(json.dumps(out), flush=True)
 
 
 def run_serve(args):
