@@ -126,8 +126,8 @@ template <int W, bool FIRE, bool COL>
 hipError_t launch_decode(const void *src, const spz::Geom &g, void *dst, int32_t *status, hipStream_t stream) {
     using T = typename spz::Elem<W>::T;
     if (g.nseg == 0) return hipGetLastError();
-    if (chunked_ok(g, W, dst) && (g.D & (g.D - 1)) == 0 && g.D <= 16) {
-        const uint32_t spw = 64u * spz::kPcConsumers / g.D;
+    if (chunked_ok(g, W, dst) && g.D <= 16) {
+        const uint32_t spw = spz::pc_spw(g.D, spz::kPcProducers, spz::kPcConsumers);
         const uint32_t grid = (g.nseg + spw - 1) / spw;
         switch (g.D) {
 #define SPZ_PC(D_)                                                                                        \
@@ -136,7 +136,8 @@ hipError_t launch_decode(const void *src, const spz::Geom &g, void *dst, int32_t
                            dim3(64 * (spz::kPcProducers + spz::kPcConsumers)), 0, stream, (const uint8_t *)src, \
                            g, (T *)dst, status);                                                          \
         break;
-            SPZ_PC(1) SPZ_PC(2) SPZ_PC(4) SPZ_PC(8) SPZ_PC(16)
+            SPZ_PC(1) SPZ_PC(2) SPZ_PC(3) SPZ_PC(4) SPZ_PC(5) SPZ_PC(6) SPZ_PC(7) SPZ_PC(8)
+            SPZ_PC(9) SPZ_PC(10) SPZ_PC(11) SPZ_PC(12) SPZ_PC(13) SPZ_PC(14) SPZ_PC(15) SPZ_PC(16)
 #undef SPZ_PC
         }
     } else if (chunked_ok(g, W, dst)) {
@@ -302,14 +303,11 @@ hipError_t launch_decode_any(const void *d_src, const spz_info *info, const spz:
 
 // Batched decoding: the workgroup kernels of one class (w, forecaster, D)
 // share one compiled form; a plan holds one work list per class.
-constexpr int kClasses = 2 * 2 * 5;   // w in {8, 16} x forecaster x D in {1, 2, 4, 8, 16}
-int class_of(uint32_t w, bool fire, uint32_t D) {
-    int d = D == 1 ? 0 : D == 2 ? 1 : D == 4 ? 2 : D == 8 ? 3 : 4;
-    return ((w == 16) * 2 + fire) * 5 + d;
-}
-uint32_t class_D(int c) { return 1u << (c % 5); }
-uint32_t class_w(int c) { return (c / 10) ? 16 : 8; }
-bool class_fire(int c) { return (c / 5) % 2; }
+constexpr int kClasses = 2 * 2 * 16;   // w in {8, 16} x forecaster x D in 1..16
+int class_of(uint32_t w, bool fire, uint32_t D) { return ((w == 16) * 2 + fire) * 16 + (int)(D - 1); }
+uint32_t class_D(int c) { return (uint32_t)(c % 16) + 1; }
+uint32_t class_w(int c) { return (c / 32) ? 16 : 8; }
+bool class_fire(int c) { return (c / 16) % 2; }
 
 template <int W, bool FIRE, int D>
 hipError_t launch_batch_class(const spz::PcStream *streams, const uint64_t *entries, const uint32_t *group_s,
@@ -389,13 +387,12 @@ spz_status build_plan(const spz_batch_item *items, const spz_info *infos, uint32
         if (st != SPZ_OK) return st;
         const spz_info &in = infos[i];
         const uint32_t D = in.D;
-        const bool pow2 = (D & (D - 1)) == 0 && D <= 16;
-        if (pow2 && in.params.hdr_group == 0 && !((uintptr_t)items[i].d_dst & 15) &&
+        if (D >= 1 && D <= 16 && in.params.hdr_group == 0 && !((uintptr_t)items[i].d_dst & 15) &&
             ((uint64_t)in.params.seg_rows * D * (in.w / 8)) % 16 == 0 && in.nseg > 0)
             cls[i] = class_of(in.w, in.params.forecaster == SPZ_FIRE, D);
     }
     // work lists: per class, streams ordered by seg_rows so that a group of
-    // segments never mixes two seg_rows; a group holds 64 * consumers / D entries
+    // segments never mixes two seg_rows; a group holds one workgroup's segments
     std::vector<std::vector<uint64_t>> ent(kClasses);
     std::vector<std::vector<uint32_t>> gs(kClasses);
     std::vector<uint32_t> order(n);
@@ -411,7 +408,7 @@ spz_status build_plan(const spz_batch_item *items, const spz_info *infos, uint32
             continue;
         }
         const int c = cls[i];
-        const uint32_t spw = 64u * spz::kPcConsumers / class_D(c);
+        const uint32_t spw = spz::pc_spw(class_D(c), spz::kPcProducers, spz::kPcConsumers);
         const uint32_t S = infos[i].params.seg_rows;
         for (uint32_t sg = 0; sg < infos[i].nseg; ++sg) {
             if (ent[c].size() % spw == 0 || gs[c].back() != S) {
@@ -423,7 +420,7 @@ spz_status build_plan(const spz_batch_item *items, const spz_info *infos, uint32
     }
     size_t bytes = sizeof(spz::PcStream) * (size_t)n + 16 + sizeof(uint32_t) * kClasses;
     for (int c = 0; c < kClasses; ++c) {
-        const uint32_t spw = 64u * spz::kPcConsumers / class_D(c);
+        const uint32_t spw = spz::pc_spw(class_D(c), spz::kPcProducers, spz::kPcConsumers);
         while (ent[c].size() % spw) ent[c].push_back(~0ull);
         bytes += ent[c].size() * 8 + gs[c].size() * 4 + 16;
     }
@@ -465,7 +462,10 @@ spz_status build_plan(const spz_batch_item *items, const spz_info *infos, uint32
         b->ngroups[c] = (uint32_t)gs[c].size();
         uint32_t cap = 1;
 #define SPZ_CAP(W_, F_, D_) if (class_w(c) == W_ && class_fire(c) == F_ && class_D(c) == D_) cap = batch_grid_cap<W_, F_, D_>();
-#define SPZ_CAPD(W_, F_) SPZ_CAP(W_, F_, 1) SPZ_CAP(W_, F_, 2) SPZ_CAP(W_, F_, 4) SPZ_CAP(W_, F_, 8) SPZ_CAP(W_, F_, 16)
+#define SPZ_CAPD(W_, F_)                                                                                \
+    SPZ_CAP(W_, F_, 1) SPZ_CAP(W_, F_, 2) SPZ_CAP(W_, F_, 3) SPZ_CAP(W_, F_, 4) SPZ_CAP(W_, F_, 5) SPZ_CAP(W_, F_, 6)   \
+    SPZ_CAP(W_, F_, 7) SPZ_CAP(W_, F_, 8) SPZ_CAP(W_, F_, 9) SPZ_CAP(W_, F_, 10) SPZ_CAP(W_, F_, 11)               \
+    SPZ_CAP(W_, F_, 12) SPZ_CAP(W_, F_, 13) SPZ_CAP(W_, F_, 14) SPZ_CAP(W_, F_, 15) SPZ_CAP(W_, F_, 16)
         if (b->ngroups[c]) { SPZ_CAPD(8, false) SPZ_CAPD(8, true) SPZ_CAPD(16, false) SPZ_CAPD(16, true) }
 #undef SPZ_CAPD
 #undef SPZ_CAP
@@ -541,7 +541,10 @@ spz_status sprintz_batch_decompress(const spz_batch *b, int32_t *d_status, hipSt
     if (class_w(c) == W_ && class_fire(c) == F_ && class_D(c) == D_)                                            \
         e = launch_batch_class<W_, F_, D_>(b->streams, b->entries[c], b->group_s[c], b->ngroups[c], b->queues + c, \
                                            d_status, b->grid[c], stream);
-#define SPZ_BLD(W_, F_) SPZ_BL(W_, F_, 1) SPZ_BL(W_, F_, 2) SPZ_BL(W_, F_, 4) SPZ_BL(W_, F_, 8) SPZ_BL(W_, F_, 16)
+#define SPZ_BLD(W_, F_)                                                                                   \
+    SPZ_BL(W_, F_, 1) SPZ_BL(W_, F_, 2) SPZ_BL(W_, F_, 3) SPZ_BL(W_, F_, 4) SPZ_BL(W_, F_, 5) SPZ_BL(W_, F_, 6)         \
+    SPZ_BL(W_, F_, 7) SPZ_BL(W_, F_, 8) SPZ_BL(W_, F_, 9) SPZ_BL(W_, F_, 10) SPZ_BL(W_, F_, 11)                     \
+    SPZ_BL(W_, F_, 12) SPZ_BL(W_, F_, 13) SPZ_BL(W_, F_, 14) SPZ_BL(W_, F_, 15) SPZ_BL(W_, F_, 16)
         SPZ_BLD(8, false) SPZ_BLD(8, true) SPZ_BLD(16, false) SPZ_BLD(16, true)
 #undef SPZ_BLD
 #undef SPZ_BL

@@ -1,5 +1,5 @@
 // Producer/consumer Sprintz decoder for gfx950 (header group = whole
-// segment, D a power of two up to 16).
+// segment, D up to 16).
 //
 // Paper: Algorithm 2 (decodeBlock) with the forecasters of Section 4.2. Of
 // the decoding work only the forecaster recurrence is serial (Section 5.4
@@ -86,11 +86,20 @@ __device__ __forceinline__ uint32_t lds_bits32(const uint32_t *w, uint32_t p) {
     return __builtin_amdgcn_alignbit(q[1], q[0], p);
 }
 
+// Segments per workgroup: the whole column groups that NC consumer
+// wavefronts hold, rounded down to a multiple of the producer count.
+__host__ __device__ constexpr uint32_t pc_spw(uint32_t D, uint32_t NP, uint32_t NC) {
+    return (64 * NC / D) / NP * NP;
+}
+__host__ __device__ constexpr uint32_t pc_pow2(uint32_t D) { return D <= 1 ? 1u : 2 * pc_pow2((D + 1) / 2); }
+
 template <int W, int D, int CB, int NP, int NC> struct PcGeom {
     static constexpr uint32_t HB = W == 8 ? 3 : 4;
     static constexpr uint32_t WB = W / 8;
-    static constexpr uint32_t CHAINS = 64 * NC;                    // column chains per workgroup
-    static constexpr uint32_t SPW = CHAINS / D;                    // segments per workgroup
+    static constexpr uint32_t DP = pc_pow2(D);                     // unpack lanes per (segment, block)
+    static constexpr uint32_t CHAINS = 64 * NC;                    // consumer lanes per workgroup
+    static constexpr uint32_t SPW = pc_spw(D, NP, NC);             // segments per workgroup
+    static constexpr uint32_t USED = SPW * D;                      // consumer lanes with a column chain
     static constexpr uint32_t SPP = SPW / NP;                      // segments per producer wave
     static constexpr uint32_t MAXREC = 8 * D * WB;                 // largest record payload
     static constexpr uint32_t HU = (CB * D * HB / 8 + 28 + 15) / 16;   // header window units
@@ -100,11 +109,11 @@ template <int W, int D, int CB, int NP, int NC> struct PcGeom {
     static constexpr uint32_t PPASS = (PAIRS + 63) / 64;           // parse passes
     static constexpr uint32_t SUNITS = SPP * NU;                   // staged units per producer
     static constexpr uint32_t SPASS = (SUNITS + 63) / 64;
-    static constexpr uint32_t ITEMS = SPP * CB * D;                // unpack items per producer
+    static constexpr uint32_t ITEMS = SPP * CB * DP;               // unpack items per producer
     static constexpr uint32_t IPASS = (ITEMS + 63) / 64;
     static constexpr uint32_t ZSTR = CB * 8 * WB + 16;             // error buffer bytes per chain
     static constexpr bool WIDE = D * WB >= 16;
-    static constexpr uint32_t OSEG = CB * 8 * D * WB + (WIDE ? D * WB : 4);  // row image stride
+    static constexpr uint32_t OSEG = CB * 8 * D * WB + (WIDE ? (D * WB + 15) & ~15u : 4);  // row image stride
     static constexpr uint32_t UPL = CB * 8 * WB / 16;              // 16-byte output units per lane
 };
 
@@ -169,12 +178,15 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
     constexpr uint32_t HB = G::HB, WB = G::WB, SPW = G::SPW, SPP = G::SPP, HU = G::HU, NU = G::NU;
     constexpr uint32_t ZSTR = G::ZSTR, OSEG = G::OSEG;
     constexpr bool ROW = D * W > 32;   // row-major payloads (reading R13)
-    static_assert(SPP * NP == SPW && CB <= 16 && 64 % SPP == 0, "geometry");
+    static_assert(SPP * NP == SPW && SPP >= 1 && SPP <= 64 && CB <= 16 && G::DP <= 16, "geometry");
 
     // One LDS arena, staging windows first: field addresses then need no base.
     constexpr uint32_t O_ZB = SPW * NU * 16;                       // [segment][header window | payload window]
     constexpr uint32_t O_OUT = O_ZB + 2 * G::CHAINS * ZSTR;        // [buffer][chain] errors of a chunk
-    constexpr uint32_t O_REC = (O_OUT + SPW * OSEG + 15) & ~15u;   // [segment] output rows of a chunk
+    // [segment] output rows of a chunk, plus a discard image for consumer
+    // lanes without a column chain (D not dividing the wavefront)
+    constexpr uint32_t NOUT = G::USED < G::CHAINS ? SPW + 1 : SPW;
+    constexpr uint32_t O_REC = (O_OUT + NOUT * OSEG + 15) & ~15u;
     constexpr uint32_t O_BM = O_REC + SPW * CB * 16;               // [segment][candidate]: codes lo, hi, payload bit, bits per row
     constexpr uint32_t O_SEG = (O_BM + SPW * CB * 4 + 15) & ~15u;  // [segment][block]: candidate or kPcZero
     constexpr uint32_t O_END = O_SEG + SPW * (uint32_t)sizeof(PcSeg);
@@ -200,7 +212,8 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
     // so it reads that segment's state once per chunk
     constexpr uint32_t LPS = 64 / SPP;                  // lanes per segment
     constexpr uint32_t SP2 = (NU + LPS - 1) / LPS;      // units per lane
-    const uint32_t st_s = ps0 + lane / LPS, st_k = lane % LPS;
+    const bool st_on = lane < LPS * SPP;
+    const uint32_t st_s = ps0 + min(lane / LPS, SPP - 1), st_k = lane % LPS;
     u32x4 reg[SP2];
     auto stage_issue = [&]() {
         const PcSeg &sg = SEG[st_s];
@@ -212,7 +225,7 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
             const uint32_t off = k < HU ? hbase + 16 * k : pbase + 16 * (k - HU);
             u32x4 v = {0u, 0u, 0u, 0u};
             // only whole 16-byte units inside the segment (its extent is a multiple of 16)
-            if (k < NU && off + 16 <= ext) v = gld128(src + off);
+            if (st_on && k < NU && off + 16 <= ext) v = gld128(src + off);
             reg[t] = v;
         }
     };
@@ -220,7 +233,7 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
 #pragma unroll
         for (uint32_t t = 0; t < SP2; ++t) {
             const uint32_t k = st_k + LPS * t;
-            if (k < NU) STG[st_s * NU + k] = reg[t];
+            if (st_on && k < NU) STG[st_s * NU + k] = reg[t];
         }
     };
     if (!consumer) {
@@ -233,13 +246,14 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
 
     // ---- consumer state: one column chain per lane ----------------------------
     const uint32_t chain = (wave - NP) * 64 + lane;   // consumers only
-    const uint32_t cs = chain / D, cj = chain % D;
+    const bool c_on = chain < G::USED;
+    const uint32_t cs = c_on ? chain / D : SPW, cj = c_on ? chain % D : 0u;
     uint32_t x = 0;
     int32_t delta = 0, acc = 0;
     uint32_t c_sh = 0, c_nb = 0;
     int32_t c_lo = 0, c_hi = 0;
     uint8_t *c_dst = nullptr;
-    if (consumer) {
+    if (consumer && c_on) {
         const PcSeg &q = SEG[cs];
         c_sh = q.sh; c_lo = q.acc_lo; c_hi = q.acc_hi; c_dst = q.dst; c_nb = q.nrow >> 3;
     }
@@ -313,7 +327,7 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
             wave_sync();
             // ---- stage the next chunk's windows -----------------------------
             if (c + 1 < nchunks) stage_issue();
-            // ---- unpack: lanes = (segment, block, column) --------------------
+            // ---- unpack: lanes = (segment, block, column < DP) ---------------
             // All LDS reads of the chunk's items are issued in three batches
             // (block map, records, fields) so that their latency is paid
             // three times per chunk rather than three times per item.
@@ -323,22 +337,22 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
 #pragma unroll
             for (uint32_t ip = 0; ip < IP; ++ip) {
                 const uint32_t it = lane + 64 * ip;
-                const uint32_t b = (it / D) % CB, s = ps0 + min(it / (D * CB), SPP - 1);
+                const uint32_t b = (it / G::DP) % CB, s = ps0 + min(it / (G::DP * CB), SPP - 1);
                 kk[ip] = BM[s * CB + b];
             }
             u32x4 rr[IP];
 #pragma unroll
             for (uint32_t ip = 0; ip < IP; ++ip) {
                 const uint32_t it = lane + 64 * ip;
-                const uint32_t s = ps0 + min(it / (D * CB), SPP - 1);
+                const uint32_t s = ps0 + min(it / (G::DP * CB), SPP - 1);
                 rr[ip] = REC[s * CB + (kk[ip] & (CB - 1))];
             }
             uint32_t fw[IP][8][2], wd[IP];
 #pragma unroll
             for (uint32_t ip = 0; ip < IP; ++ip) {
                 const uint32_t it = lane + 64 * ip;
-                const uint32_t j = it % D;
-                const bool nz = it < G::ITEMS && kk[ip] != kPcZero;
+                const uint32_t j = it % G::DP;
+                const bool nz = it < G::ITEMS && j < (uint32_t)D && kk[ip] != kPcZero;
                 const u32x4 rec = rr[ip];
                 const uint32_t bp = j * HB;
                 const uint32_t code = !nz ? 0u
@@ -346,7 +360,7 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
                                       : bp >= 32      ? __builtin_amdgcn_ubfe(rec.y, bp - 32, HB)
                                                       : __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(rec.y, rec.x, bp), 0, HB);
                 const uint32_t width = code + ((code + 1) >> HB);   // code w-1 stands for width w
-                const uint32_t off = pc_incl<D>(width, j) - width;
+                const uint32_t off = pc_incl<G::DP>(width, j) - width;
                 const uint32_t p0 = nz ? rec.z + (ROW ? off : 8 * off) : 0u;
                 const uint32_t step = !nz ? 0u : ROW ? rec.w : width;
                 wd[ip] = width;
@@ -362,11 +376,11 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
 #pragma unroll
             for (uint32_t ip = 0; ip < IP; ++ip) {
                 const uint32_t it = lane + 64 * ip;
-                const uint32_t j = it % D, b = (it / D) % CB, s = ps0 + min(it / (D * CB), SPP - 1);
+                const uint32_t j = it % G::DP, b = (it / G::DP) % CB, s = ps0 + min(it / (G::DP * CB), SPP - 1);
                 uint32_t z[8];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) z[i] = __builtin_amdgcn_ubfe(fw[ip][i][0], 0, wd[ip]);
-                if (it < G::ITEMS) {
+                if (it < G::ITEMS && j < (uint32_t)D) {
                     uint8_t *zp = zbuf + (s * D + j) * ZSTR + b * 8 * WB;
                     // zigzag fields packed 2 (or 4) per dword, then unzigzagged lane-wise:
                     // e = (z >> 1) ^ -(z & 1) in every 16-bit (8-bit) lane

@@ -46,10 +46,7 @@ struct EncSlot {
     uint64_t base;      // write pass: container byte offset of the segment
 };
 
-__host__ __device__ inline uint32_t enc_chunk_blocks(uint32_t dp_log2) {
-    const uint32_t v = 4u << dp_log2;
-    return v < (uint32_t)kEncChunkBlocks ? v : (uint32_t)kEncChunkBlocks;
-}
+__host__ __device__ inline uint32_t enc_chunk_blocks(uint32_t) { return (uint32_t)kEncChunkBlocks; }
 
 // Header bytes of a whole segment with nblk blocks at most (fast-path limit).
 __host__ __device__ inline uint32_t enc_hdr_cap(uint32_t nblk, uint32_t D, uint32_t w) {
@@ -90,6 +87,10 @@ __global__ __launch_bounds__(kThreads) void k_encode_chunked(const uint8_t *__re
     const uint32_t xs_seg = CR * D * WB;                        // staged bytes per segment
     const uint32_t out_seg = (CB * 8 * D * WB + 6 * CB + 15) & ~15u;  // payload staging bytes per segment
     const uint32_t hdr_seg = (enc_hdr_cap(g.S >> 3, D, W) + 15) & ~15u;
+    // container words one segment's chunk payload can touch (a misaligned
+    // start adds one), and the magic multiplier dividing by that count
+    const uint32_t out_wps = out_seg / 4 + 1;
+    const uint64_t wps_magic = ((1ull << 32) + out_wps - 1) / out_wps;
 
     // bounded views: this workgroup's input rows and the whole container
     const uint64_t wrow0 = (uint64_t)seg0 * g.S;
@@ -283,8 +284,9 @@ __global__ __launch_bounds__(kThreads) void k_encode_chunked(const uint8_t *__re
         __syncthreads();
 
         // ---- records: runs, record indices, payload offsets ----------------
-        if (tid < SPW * CB) {
-            const uint32_t s = tid / CB, q = tid % CB;
+        // lanes = (segment, block); whole lane groups of CB stay together
+        for (uint32_t rl = tid; rl < SPW * CB; rl += kThreads) {
+            const uint32_t s = rl / CB, q = rl % CB;
             const uint32_t bic = s < nsw ? blocks_in_chunk(s, c) : 0u;
             const EncSlot sl = slots[s];
             const bool act = q < bic;
@@ -375,32 +377,33 @@ __global__ __launch_bounds__(kThreads) void k_encode_chunked(const uint8_t *__re
             __syncthreads();
 
             // ---- payload bytes out; clear the staging -----------------------
-            // staging byte b of segment s belongs at container byte o0 + b
-            for (uint32_t s = 0; s < nsw; ++s) {
+            // staging byte b of segment s belongs at container byte o0 + b;
+            // lanes = (segment, container word), all segments at once
+            for (uint32_t it = tid; it < nsw * out_wps; it += kThreads) {
+                const uint32_t s = (uint32_t)(((uint64_t)it * wps_magic) >> 32);
+                const uint32_t k = it - s * out_wps;
                 const EncSlot sl = slots[s];
                 const uint32_t n = sl.cursor - sl.pad;     // payload bytes of this chunk
-                if (n == 0) continue;
                 const uint64_t o0 = sl.base + 4 + sl.hdr_bytes + sl.pad;
-                const uint32_t *op = &OUTP[s * (out_seg / 4)];
                 const uint32_t mis = (uint32_t)(o0 & 3);
-                const uint32_t nw = (mis + n + 3) >> 2;    // container words touched
-                for (uint32_t k = tid; k < nw; k += kThreads) {
-                    // container word k holds staging bytes 4k - mis .. 4k - mis + 3
-                    const uint32_t cur = k < (n + 3) / 4 ? op[k] : 0u;
-                    const uint32_t word = mis == 0 ? cur
-                                                   : __builtin_amdgcn_alignbit(cur, k > 0 ? op[k - 1] : 0u, 8 * (4 - mis));
-                    const uint64_t addr = (o0 & ~3ull) + 4ull * k;
-                    const int32_t b0 = 4 * (int32_t)k - (int32_t)mis;
-                    if (b0 >= 0 && (uint32_t)b0 + 4 <= n) {
-                        if (addr + 4 <= g.cap) *reinterpret_cast<uint32_t *>(dst + addr) = word;
+                const uint32_t nw = n == 0 ? 0u : (mis + n + 3) >> 2;    // container words touched
+                if (k >= nw) continue;
+                const uint32_t *op = &OUTP[s * (out_seg / 4)];
+                // container word k holds staging bytes 4k - mis .. 4k - mis + 3
+                const uint32_t cur = k < (n + 3) / 4 ? op[k] : 0u;
+                const uint32_t word = mis == 0 ? cur
+                                               : __builtin_amdgcn_alignbit(cur, k > 0 ? op[k - 1] : 0u, 8 * (4 - mis));
+                const uint64_t addr = (o0 & ~3ull) + 4ull * k;
+                const int32_t b0 = 4 * (int32_t)k - (int32_t)mis;
+                if (b0 >= 0 && (uint32_t)b0 + 4 <= n) {
+                    if (addr + 4 <= g.cap) *reinterpret_cast<uint32_t *>(dst + addr) = word;
+                    else any_err = 1;
+                } else {
+                    for (uint32_t t = 0; t < 4; ++t) {
+                        const int32_t bb = b0 + (int32_t)t;
+                        if (bb < 0 || (uint32_t)bb >= n) continue;
+                        if (addr + t < g.cap) dst[addr + t] = (uint8_t)(word >> (8 * t));
                         else any_err = 1;
-                    } else {
-                        for (uint32_t t = 0; t < 4; ++t) {
-                            const int32_t bb = b0 + (int32_t)t;
-                            if (bb < 0 || (uint32_t)bb >= n) continue;
-                            if (addr + t < g.cap) dst[addr + t] = (uint8_t)(word >> (8 * t));
-                            else any_err = 1;
-                        }
                     }
                 }
             }
@@ -441,35 +444,46 @@ __global__ __launch_bounds__(kThreads) void k_encode_chunked(const uint8_t *__re
     }
     if (WRITE) {
         __syncthreads();
-        // header arrays (dword aligned start), raw tail rows, zero padding
-        for (uint32_t s = 0; s < nsw; ++s) {
+        // header arrays (dword aligned start); lanes = (segment, header word)
+        const uint32_t hwps = hdr_seg / 4;
+        const uint64_t hw_magic = ((1ull << 32) + hwps - 1) / hwps;
+        for (uint32_t it = tid; it < nsw * hwps; it += kThreads) {
+            const uint32_t s = (uint32_t)(((uint64_t)it * hw_magic) >> 32);
+            const uint32_t k = it - s * hwps;
             const EncSlot sl = slots[s];
-            const uint32_t seg = seg0 + s;
             const uint32_t hdr = sl.hdr_bytes;
-            const uint32_t *hw = &OUTH[s * (hdr_seg / 4)];
-            for (uint32_t k = tid; k < (hdr + 3) / 4; k += kThreads) {
-                const uint64_t addr = sl.base + 4 + 4ull * k;
-                if (4 * k + 4 <= hdr) {
-                    if (addr + 4 <= g.cap) *reinterpret_cast<uint32_t *>(dst + addr) = hw[k];
+            if (4 * k >= hdr) continue;
+            const uint32_t hv = OUTH[s * hwps + k];
+            const uint64_t addr = sl.base + 4 + 4ull * k;
+            if (4 * k + 4 <= hdr) {
+                if (addr + 4 <= g.cap) *reinterpret_cast<uint32_t *>(dst + addr) = hv;
+                else any_err = 1;
+            } else {
+                for (uint32_t t = 0; 4 * k + t < hdr; ++t) {
+                    if (addr + t < g.cap) dst[addr + t] = (uint8_t)(hv >> (8 * t));
                     else any_err = 1;
-                } else {
-                    for (uint32_t t = 0; 4 * k + t < hdr; ++t) {
-                        if (addr + t < g.cap) dst[addr + t] = (uint8_t)(hw[k] >> (8 * t));
-                        else any_err = 1;
-                    }
                 }
             }
+        }
+        // raw tail rows and zero padding to the 16-byte segment end;
+        // lanes = (segment, byte): fewer than 8 rows plus 15 bytes each
+        const uint32_t tbps = 7 * D * WB + 16;
+        const uint64_t tb_magic = ((1ull << 32) + tbps - 1) / tbps;
+        for (uint32_t it = tid; it < nsw * tbps; it += kThreads) {
+            const uint32_t s = (uint32_t)(((uint64_t)it * tb_magic) >> 32);
+            const uint32_t t = it - s * tbps;
+            const EncSlot sl = slots[s];
+            const uint32_t seg = seg0 + s;
             const uint32_t tail_bytes = sl.tail * D * WB;
-            const uint64_t tpos = sl.base + 4 + hdr + sl.cursor;
-            const uint64_t trow = (uint64_t)seg * g.S + (uint64_t)sl.nblk * 8;
+            const uint64_t tpos = sl.base + 4 + sl.hdr_bytes + sl.cursor;
             const uint64_t end = sl.base + sl.pad;
-            for (uint64_t p = tpos + tid; p < end; p += kThreads) {
-                uint32_t v = 0;
-                const uint64_t t = p - tpos;
-                if (t < tail_bytes) v = buf_ld8(in, (uint32_t)((trow - wrow0) * D * WB + t));
-                if (p < g.cap) dst[p] = (uint8_t)v;
-                else any_err = 1;
-            }
+            const uint64_t p = tpos + t;
+            if (p >= end) continue;
+            const uint64_t trow = (uint64_t)seg * g.S + (uint64_t)sl.nblk * 8;
+            uint32_t v = 0;
+            if (t < tail_bytes) v = buf_ld8(in, (uint32_t)((trow - wrow0) * D * WB + t));
+            if (p < g.cap) dst[p] = (uint8_t)v;
+            else any_err = 1;
         }
     }
     if (WRITE && any_err && status) atomicOr(status, 2);

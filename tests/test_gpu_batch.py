@@ -2,9 +2,9 @@
 
 Many containers, written by the CPU oracle, decoded in one call: every output
 must equal its input exactly, and equal what sprintz_decompress gives for the
-same container. Covers every batched class shape (D = 1, 2, 4, 8, 16, 8- and
-16-bit, both forecasters, several seg_rows in one plan), streams that take the
-single-container path inside the same call (D = 3, grouped headers), empty
+same container. Covers batched class shapes (D from 1 to 16, 8- and 16-bit,
+both forecasters, several seg_rows in one plan), streams that take the
+single-container path inside the same call (D = 20, grouped headers), empty
 streams, repeated runs of one plan, corrupt containers, and replays of a
 captured HIP graph."""
 import sys
@@ -38,7 +38,7 @@ def _streams(seed=0, n=24):
     rng = np.random.default_rng(seed)
     out = []
     for k in range(n):
-        D = int(rng.choice([1, 2, 4, 8, 16]))
+        D = int(rng.integers(1, 17))
         dt = [np.int8, np.uint8, np.int16, np.uint16][k % 4]
         rows = int(rng.integers(0, 5000)) if k % 7 else int(rng.integers(0, 20))
         S = int(rng.choice([16, 64, 256, 1024]))
@@ -47,7 +47,7 @@ def _streams(seed=0, n=24):
         x = datagen.ar2_uint16(rows, D, sigma=float(rng.uniform(0.5, 200)), seed=1000 + k).astype(dt)
         out.append((x, ["fire", "delta"][k % 3 == 0], S, 0))
     # single-container path inside the batch call
-    out.append((datagen.walk_int8(3001, 3, seed=7), "fire", 1024, 0))
+    out.append((datagen.walk_int8(3001, 20, seed=7), "fire", 1024, 0))
     out.append((datagen.ar2_uint16(2000, 8, seed=8), "fire", 256, 2))
     out.append((np.zeros((0, 4), np.int16), "fire", 1024, 0))
     return out

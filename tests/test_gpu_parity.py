@@ -112,6 +112,15 @@ def test_random_corpus():
         _check(x, f, S, G, ls, label=f"corpus#{k}")
 
 
+@pytest.mark.parametrize("D", [3, 5, 6, 7, 11, 12])
+def test_non_power_of_two_columns(D):
+    # column counts that leave consumer lanes idle (64 mod D != 0), over
+    # many workgroups and a ragged tail
+    for dt, f in ((np.uint16, "fire"), (np.int8, "delta"), (np.uint8, "fire")):
+        x = datagen.ar2_uint16(150000 + 13, D, sigma=40, seed=D).astype(dt)
+        _check(x, f, 1024, label=f"D={D}")
+
+
 @pytest.mark.parametrize("rows", [0, 1, 7, 8, 9, 15, 16, 17, 1023, 1024, 1025])
 @pytest.mark.parametrize("D", [1, 3, 64])
 def test_degenerate_sizes(rows, D):
@@ -149,8 +158,9 @@ def test_repeatable():
     assert a == b
 
 
-def test_corrupt_containers_flag_status_and_stay_in_bounds():
-    x = datagen.ar2_uint16(40000, 8, seed=3)
+@pytest.mark.parametrize("D", [8, 5])
+def test_corrupt_containers_flag_status_and_stay_in_bounds(D):
+    x = datagen.ar2_uint16(40000, D, seed=3)
     ref = bytearray(oracle.compress(x, "fire", 1024))
     info = spz.sprintz_get_info(bytes(ref[:64]))
     rng = np.random.default_rng(5)
