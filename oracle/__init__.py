@@ -80,6 +80,20 @@ def _load():
     lib.oracle_code_of_nbits.restype = ctypes.c_int
     lib.oracle_width_of_code.argtypes = [ctypes.c_int, ctypes.c_int]
     lib.oracle_width_of_code.restype = ctypes.c_int
+    lib.oracle_huff_lengths.argtypes = [vp, vp]
+    lib.oracle_huff_lengths.restype = ctypes.c_int
+    lib.oracle_entropy_bound.argtypes = [vp, sz]
+    lib.oracle_entropy_bound.restype = sz
+    lib.oracle_entropy_encode.argtypes = [vp, sz, vp, sz, ctypes.POINTER(sz)]
+    lib.oracle_entropy_encode.restype = ctypes.c_int
+    lib.oracle_entropy_decode.argtypes = [vp, sz, vp, sz, ctypes.POINTER(sz)]
+    lib.oracle_entropy_decode.restype = ctypes.c_int
+    lib.oracle_entropy_plain_size.argtypes = [vp, sz]
+    lib.oracle_entropy_plain_size.restype = sz
+    lib.oracle_huff_encode_segment.argtypes = [vp, sz, vp, sz]
+    lib.oracle_huff_encode_segment.restype = sz
+    lib.oracle_huff_decode_segment.argtypes = [vp, sz, vp, sz, ctypes.POINTER(sz)]
+    lib.oracle_huff_decode_segment.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -102,9 +116,10 @@ def compress_bound(rows: int, D: int, dtype, seg_rows: int, hdr_group: int = 0) 
 
 
 def compress(x: np.ndarray, forecaster: str = "fire", seg_rows: int | None = None, hdr_group: int = 0,
-             learn_shift: int = 1) -> bytes:
+             learn_shift: int = 1, entropy: int = 0) -> bytes:
     """Compress a (rows, D) array. ``seg_rows=None`` codes the whole series as
-    one segment (the paper's single stream)."""
+    one segment (the paper's single stream). ``entropy=1`` adds the Huffman
+    stage to every segment."""
     x = _as_2d(x)
     rows, D = x.shape
     if seg_rows is None:
@@ -116,7 +131,68 @@ def compress(x: np.ndarray, forecaster: str = "fire", seg_rows: int | None = Non
                                  hdr_group, learn_shift, out.ctypes.data, cap, ctypes.byref(size))
     if rc != 0:
         raise OracleError(rc)
+    plain = out[: size.value].tobytes()
+    return entropy_encode(plain) if entropy else plain
+
+
+def entropy_encode(plain: bytes) -> bytes:
+    """Plain container -> Huffman-coded container (Section 4.3's entropy stage)."""
+    src = np.frombuffer(plain, dtype=np.uint8)
+    cap = int(_load().oracle_entropy_bound(src.ctypes.data, len(plain)))
+    if cap == 0:
+        raise OracleError(-1)
+    out = np.zeros(cap, dtype=np.uint8)
+    size = ctypes.c_size_t(0)
+    rc = _load().oracle_entropy_encode(src.ctypes.data, len(plain), out.ctypes.data, cap, ctypes.byref(size))
+    if rc != 0:
+        raise OracleError(rc)
     return out[: size.value].tobytes()
+
+
+def entropy_decode(coded: bytes) -> bytes:
+    """Huffman-coded container -> the plain container it was made from."""
+    src = np.frombuffer(coded, dtype=np.uint8)
+    cap = int(_load().oracle_entropy_plain_size(src.ctypes.data, len(coded)))
+    if cap == 0:
+        raise OracleError(-3)
+    out = np.zeros(cap, dtype=np.uint8)
+    size = ctypes.c_size_t(0)
+    rc = _load().oracle_entropy_decode(src.ctypes.data, len(coded), out.ctypes.data, cap, ctypes.byref(size))
+    if rc != 0:
+        raise OracleError(rc)
+    return out[: size.value].tobytes()
+
+
+def huff_lengths(counts) -> np.ndarray:
+    """Code lengths (0 = absent) the entropy stage gives 256 byte counts."""
+    c = np.ascontiguousarray(np.asarray(counts, dtype=np.uint64))
+    assert c.shape == (256,)
+    out = np.zeros(256, dtype=np.uint8)
+    rc = _load().oracle_huff_lengths(c.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise OracleError(rc)
+    return out
+
+
+def huff_encode_segment(plain: bytes) -> bytes:
+    """Entropy-code one plain segment (length a multiple of 16)."""
+    src = np.frombuffer(plain, dtype=np.uint8)
+    cap = 4 + 128 + 64 + (len(plain) * 11 + 7) // 8 + 16 + 16
+    out = np.zeros(cap, dtype=np.uint8)
+    n = int(_load().oracle_huff_encode_segment(src.ctypes.data, len(plain), out.ctypes.data, cap))
+    if n == 0:
+        raise OracleError(-1)
+    return out[:n].tobytes()
+
+
+def huff_decode_segment(seg: bytes, cap: int) -> bytes:
+    src = np.frombuffer(seg, dtype=np.uint8)
+    out = np.zeros(max(cap, 1), dtype=np.uint8)
+    n = ctypes.c_size_t(0)
+    rc = _load().oracle_huff_decode_segment(src.ctypes.data, len(seg), out.ctypes.data, cap, ctypes.byref(n))
+    if rc != 0:
+        raise OracleError(rc)
+    return out[: n.value].tobytes()
 
 
 def info(buf: bytes) -> tuple[int, int, np.dtype, int]:

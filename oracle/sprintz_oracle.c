@@ -618,7 +618,7 @@ static int parse_header(const uint8_t *src, size_t n, container_info *ci) {
     ci->S = (uint32_t)get_le(src + 24, 4); ci->nseg = (uint32_t)get_le(src + 28, 4);
     ci->data_bytes = get_le(src + 32, 8);
     if (check_params(ci->D, ci->dtype, ci->forecaster_id, ci->S, ci->G, ci->learn_shift)) return OR_ECORRUPT;
-    if (ci->w != dtype_bits(ci->dtype) || ci->entropy != 0) return OR_ECORRUPT;
+    if (ci->w != dtype_bits(ci->dtype) || (ci->entropy != 0 && ci->entropy != 1)) return OR_ECORRUPT;
     if (num_segments(ci->rows, ci->S) != ci->nseg) return OR_ECORRUPT;
     return OR_OK;
 }
@@ -632,8 +632,28 @@ int oracle_info(const void *src, size_t n, uint64_t *rows, uint32_t *D, int *dty
     return OR_OK;
 }
 
+static int decompress_plain(const uint8_t *src, size_t n, void *dst, size_t cap);
+size_t oracle_entropy_plain_size(const void *src_v, size_t n);
+int oracle_entropy_decode(const void *src_v, size_t n, void *dst, size_t cap, size_t *out_size);
+
 int oracle_decompress(const void *src_v, size_t n, void *dst, size_t cap) {
     const uint8_t *src = src_v;
+    container_info ci;
+    int rc = parse_header(src, n, &ci);
+    if (rc) return rc;
+    if (ci.entropy == 0) return decompress_plain(src, n, dst, cap);
+    size_t pn = oracle_entropy_plain_size(src, n);
+    if (pn == 0) return OR_ECORRUPT;
+    uint8_t *plain = malloc(pn);
+    if (!plain) return OR_ENOMEM;
+    size_t got = 0;
+    rc = oracle_entropy_decode(src, n, plain, pn, &got);
+    if (rc == OR_OK) rc = decompress_plain(plain, got, dst, cap);
+    free(plain);
+    return rc;
+}
+
+static int decompress_plain(const uint8_t *src, size_t n, void *dst, size_t cap) {
     container_info ci;
     int rc = parse_header(src, n, &ci);
     if (rc) return rc;
@@ -660,6 +680,258 @@ int oracle_decompress(const void *src_v, size_t n, void *dst, size_t cap) {
     }
     free(x);
     return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Entropy stage: Huffman coding of each segment's packed bytes              */
+/* ------------------------------------------------------------------------ */
+/*
+ * Section 4.3 ends with an entropy stage: the bit-packed bytes are Huffman
+ * coded with an off-the-shelf byte-oriented coder, bytes taken as symbols
+ * regardless of the data's bit width. The coder and its format are not part
+ * of the paper; this implementation uses its own (reading R19):
+ *   - one code per segment, built from the byte counts of the whole plain
+ *     segment (the segment exactly as the plain container holds it);
+ *   - code lengths by the two-queue Huffman construction over the present
+ *     byte values sorted by (count, value), a leaf taken before an internal
+ *     node of equal weight; lengths above 11 bits are removed by halving the
+ *     counts (c -> (c + 1) / 2, so present values stay present) and building
+ *     again; a single present value gets length 1;
+ *   - canonical codes: values sorted by (length, value), consecutive code
+ *     values, one shift left per extra bit of length;
+ *   - 16 sub-streams, sub-stream k coding plain bytes [k n/16, (k+1) n/16),
+ *     each a byte-aligned LSB-first bit string in which every code is stored
+ *     first bit (most significant) first.
+ * Entropy-coded segment:
+ *   u32 n | u8 len[128] (4 bits per byte value, even values in the low
+ *   nibble) | u32 size[16] (bytes of each sub-stream) | sub-streams | pad to 16
+ * The container header is the plain one with byte 11 = 1; its offset table
+ * and data_bytes describe the entropy-coded segments.
+ */
+#define HUF_MAXLEN 11
+#define HUF_NSUB 16
+#define HUF_FIXED (4 + 128 + 4 * HUF_NSUB)
+
+/* Code lengths of the 256 byte values from their counts (0 = absent). */
+int oracle_huff_lengths(const uint64_t *count, uint8_t *len) {
+    uint64_t f[256];
+    int order[256], n = 0;
+    for (int v = 0; v < 256; v++) { f[v] = count[v]; len[v] = 0; if (f[v]) n++; }
+    if (n == 0) return OR_OK;
+    if (n == 1) {
+        for (int v = 0; v < 256; v++) if (f[v]) len[v] = 1;
+        return OR_OK;
+    }
+    for (;;) {
+        /* present values sorted by (count, value): insertion sort */
+        int m = 0;
+        for (int v = 0; v < 256; v++) {
+            if (!f[v]) continue;
+            int k = m++;
+            while (k > 0 && (f[order[k - 1]] > f[v])) { order[k] = order[k - 1]; k--; }
+            order[k] = v;
+        }
+        /* nodes 0..m-1 are the leaves in sorted order; internal nodes follow */
+        uint64_t weight[511];
+        int parent[511];
+        for (int k = 0; k < m; k++) weight[k] = f[order[k]];
+        int leaf = 0, inner = m, next = m;
+        for (int step = 0; step < m - 1; step++) {
+            int pick[2];
+            for (int t = 0; t < 2; t++) {
+                int use_leaf = leaf < m && (inner >= next || weight[leaf] <= weight[inner]);
+                pick[t] = use_leaf ? leaf++ : inner++;
+            }
+            weight[next] = weight[pick[0]] + weight[pick[1]];
+            parent[pick[0]] = next;
+            parent[pick[1]] = next;
+            next++;
+        }
+        int maxlen = 0;
+        for (int k = 0; k < m; k++) {
+            int d = 0;
+            for (int q = k; q != next - 1; q = parent[q]) d++;
+            len[order[k]] = (uint8_t)d;
+            if (d > maxlen) maxlen = d;
+        }
+        if (maxlen <= HUF_MAXLEN) return OR_OK;
+        for (int v = 0; v < 256; v++) if (f[v]) f[v] = (f[v] + 1) / 2;
+    }
+}
+
+/* Canonical code values from the lengths. */
+static void huff_codes(const uint8_t *len, uint32_t *code) {
+    uint32_t c = 0;
+    int prev = -1;
+    for (int l = 1; l <= HUF_MAXLEN; l++)
+        for (int v = 0; v < 256; v++) {
+            if (len[v] != l) continue;
+            if (prev >= 0) c = (c + 1) << (l - prev);
+            code[v] = c;
+            prev = l;
+        }
+}
+
+static size_t huff_segment_bound(size_t n) { return align16(HUF_FIXED + (n * HUF_MAXLEN + 7) / 8 + HUF_NSUB); }
+
+/* Entropy-code one plain segment of n bytes; returns the coded size. */
+static size_t huff_encode_segment(const uint8_t *p, size_t n, uint8_t *out) {
+    uint64_t count[256] = {0};
+    uint8_t len[256];
+    uint32_t code[256] = {0};
+    for (size_t i = 0; i < n; i++) count[p[i]]++;
+    oracle_huff_lengths(count, len);
+    huff_codes(len, code);
+    put_le(out, n, 4);
+    for (int v = 0; v < 256; v += 2) out[4 + v / 2] = (uint8_t)(len[v] | (len[v + 1] << 4));
+    size_t pos = HUF_FIXED;
+    for (int k = 0; k < HUF_NSUB; k++) {
+        bit_writer bw = {out + pos, huff_segment_bound(n) - pos, 0, 0};
+        for (size_t i = k * (n / HUF_NSUB); i < (k + 1) * (n / HUF_NSUB); i++) {
+            int l = len[p[i]];
+            for (int b = l - 1; b >= 0; b--) bw_put(&bw, (code[p[i]] >> b) & 1u, 1);
+        }
+        bw_align_byte(&bw);
+        put_le(out + 4 + 128 + 4 * k, bw.bitpos / 8, 4);
+        pos += bw.bitpos / 8;
+    }
+    size_t end = align16(pos);
+    memset(out + pos, 0, end - pos);
+    return end;
+}
+
+/* Decode one entropy-coded segment of m bytes into its plain bytes. */
+static int huff_decode_segment(const uint8_t *s, size_t m, uint8_t *plain, size_t cap, size_t *n_out) {
+    if (m < HUF_FIXED) return OR_ECORRUPT;
+    size_t n = get_le(s, 4);
+    if (n % 16 || n > cap) return OR_ECORRUPT;
+    uint8_t len[256];
+    for (int v = 0; v < 256; v += 2) { len[v] = s[4 + v / 2] & 15; len[v + 1] = s[4 + v / 2] >> 4; }
+    /* canonical decoding tables: first code and first index of every length */
+    int cnt[HUF_MAXLEN + 2] = {0}, sorted[256], ns = 0;
+    for (int v = 0; v < 256; v++) {
+        if (len[v] > HUF_MAXLEN) return OR_ECORRUPT;
+        if (len[v]) cnt[len[v]]++;
+    }
+    uint32_t first[HUF_MAXLEN + 2];
+    int index[HUF_MAXLEN + 2];
+    uint32_t c = 0;
+    for (int l = 1; l <= HUF_MAXLEN; l++) {
+        first[l] = c; index[l] = ns;
+        for (int v = 0; v < 256; v++) if (len[v] == l) sorted[ns++] = v;
+        c = (c + (uint32_t)cnt[l]) << 1;
+    }
+    size_t pos = HUF_FIXED;
+    for (int k = 0; k < HUF_NSUB; k++) {
+        size_t sz = get_le(s + 4 + 128 + 4 * k, 4);
+        if (pos + sz > m) return OR_ECORRUPT;
+        bit_reader br = {s + pos, sz, 0, 0};
+        for (size_t i = k * (n / HUF_NSUB); i < (k + 1) * (n / HUF_NSUB); i++) {
+            uint32_t v = 0;
+            int l = 0, found = -1;
+            while (found < 0) {
+                if (++l > HUF_MAXLEN || br.bitpos >= 8 * sz) return OR_ECORRUPT;
+                v = (v << 1) | (uint32_t)br_get(&br, 1);
+                if (cnt[l] && v >= first[l] && v - first[l] < (uint32_t)cnt[l]) found = sorted[index[l] + (int)(v - first[l])];
+            }
+            plain[i] = (uint8_t)found;
+        }
+        pos += sz;
+    }
+    *n_out = n;
+    return OR_OK;
+}
+
+/* Test hooks: one segment (n a multiple of 16). */
+size_t oracle_huff_encode_segment(const void *plain, size_t n, void *out, size_t cap) {
+    if (n % 16 || cap < huff_segment_bound(n)) return 0;
+    return huff_encode_segment(plain, n, out);
+}
+int oracle_huff_decode_segment(const void *seg, size_t m, void *plain, size_t cap, size_t *n_out) {
+    return huff_decode_segment(seg, m, plain, cap, n_out);
+}
+
+size_t oracle_entropy_bound(const void *plain_v, size_t n) {
+    const uint8_t *src = plain_v;
+    container_info ci;
+    if (parse_header(src, n, &ci) || ci.entropy != 0) return 0;
+    size_t data_start = align16(HDR_BYTES + 8 * (size_t)(ci.nseg + 1));
+    size_t total = data_start;
+    for (uint32_t s = 0; s < ci.nseg; s++) {
+        uint64_t a = get_le(src + HDR_BYTES + 8 * (size_t)s, 8), b = get_le(src + HDR_BYTES + 8 * (size_t)(s + 1), 8);
+        total += huff_segment_bound((size_t)(b - a));
+    }
+    return total;
+}
+
+/* Plain container -> entropy-coded container. */
+int oracle_entropy_encode(const void *plain_v, size_t n, void *dst, size_t cap, size_t *out_size) {
+    const uint8_t *src = plain_v;
+    uint8_t *out = dst;
+    container_info ci;
+    int rc = parse_header(src, n, &ci);
+    if (rc) return rc;
+    if (ci.entropy != 0) return OR_EINVAL;
+    size_t data_start = align16(HDR_BYTES + 8 * (size_t)(ci.nseg + 1));
+    if (data_start + ci.data_bytes > n) return OR_ECORRUPT;
+    if (cap < oracle_entropy_bound(plain_v, n)) return OR_ENOSPC;
+    memcpy(out, src, data_start);
+    out[11] = 1;
+    size_t pos = data_start;
+    for (uint32_t s = 0; s < ci.nseg; s++) {
+        uint64_t a = get_le(src + HDR_BYTES + 8 * (size_t)s, 8), b = get_le(src + HDR_BYTES + 8 * (size_t)(s + 1), 8);
+        if (a > b || b > ci.data_bytes || a % 16 || b % 16) return OR_ECORRUPT;
+        put_le(out + HDR_BYTES + 8 * (size_t)s, pos - data_start, 8);
+        pos += huff_encode_segment(src + data_start + a, (size_t)(b - a), out + pos);
+    }
+    put_le(out + HDR_BYTES + 8 * (size_t)ci.nseg, pos - data_start, 8);
+    put_le(out + 32, pos - data_start, 8);
+    *out_size = pos;
+    return OR_OK;
+}
+
+/* Entropy-coded container -> plain container (cap >= the plain size). */
+int oracle_entropy_decode(const void *src_v, size_t n, void *dst, size_t cap, size_t *out_size) {
+    const uint8_t *src = src_v;
+    uint8_t *out = dst;
+    container_info ci;
+    int rc = parse_header(src, n, &ci);
+    if (rc) return rc;
+    if (ci.entropy != 1) return OR_EINVAL;
+    size_t data_start = align16(HDR_BYTES + 8 * (size_t)(ci.nseg + 1));
+    if (data_start + ci.data_bytes > n || cap < data_start) return OR_ECORRUPT;
+    memcpy(out, src, data_start);
+    out[11] = 0;
+    size_t pos = data_start;
+    for (uint32_t s = 0; s < ci.nseg; s++) {
+        uint64_t a = get_le(src + HDR_BYTES + 8 * (size_t)s, 8), b = get_le(src + HDR_BYTES + 8 * (size_t)(s + 1), 8);
+        if (a > b || b > ci.data_bytes || a % 16 || b % 16) return OR_ECORRUPT;
+        put_le(out + HDR_BYTES + 8 * (size_t)s, pos - data_start, 8);
+        size_t m = 0;
+        rc = huff_decode_segment(src + data_start + a, (size_t)(b - a), out + pos, cap - pos, &m);
+        if (rc) return rc;
+        pos += m;
+    }
+    put_le(out + HDR_BYTES + 8 * (size_t)ci.nseg, pos - data_start, 8);
+    put_le(out + 32, pos - data_start, 8);
+    *out_size = pos;
+    return OR_OK;
+}
+
+/* Plain size of an entropy-coded container (from its segments' n fields). */
+size_t oracle_entropy_plain_size(const void *src_v, size_t n) {
+    const uint8_t *src = src_v;
+    container_info ci;
+    if (parse_header(src, n, &ci) || ci.entropy != 1) return 0;
+    size_t data_start = align16(HDR_BYTES + 8 * (size_t)(ci.nseg + 1));
+    if (data_start + ci.data_bytes > n) return 0;
+    size_t total = data_start;
+    for (uint32_t s = 0; s < ci.nseg; s++) {
+        uint64_t a = get_le(src + HDR_BYTES + 8 * (size_t)s, 8);
+        if (a + 4 > ci.data_bytes) return 0;
+        total += get_le(src + data_start + a, 4);
+    }
+    return total;
 }
 
 /* ------------------------------------------------------------------------ */
