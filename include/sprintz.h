@@ -70,7 +70,13 @@ typedef struct {
     uint32_t hdr_group;    /* records whose headers are stored together (Section 4.3,
                               last paragraph); 0 = one group per segment */
     uint32_t learn_shift;  /* FIRE learning rate eta = 2^-learn_shift (paper: eta = 1/2) */
-    uint32_t entropy;      /* 0 = no entropy stage (the only value accepted) */
+    uint32_t entropy;      /* 0 = none; 1 = Huffman coding of every segment's packed
+                              bytes (Section 4.3, last stage; the coder and its format
+                              are this library's: one canonical code of at most 11-bit
+                              codes per segment, 16 sub-streams). Compression needs
+                              a plain container's space in the workspace; the coded
+                              segment image must fit 60 KiB of LDS
+                              (SPZ_EUNSUPPORTED otherwise) */
 } spz_params;
 
 typedef struct {
@@ -93,7 +99,9 @@ void spz_params_default(spz_params *p);
  * arguments are invalid. */
 size_t sprintz_compress_bound(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p);
 
-/* Bytes of device workspace sprintz_compress needs (8 per segment). */
+/* Bytes of device workspace sprintz_compress needs (8 per segment; with
+ * entropy = 1 also the plain container, its workspace and 256 bytes per
+ * segment for the code records). */
 size_t sprintz_workspace_size(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p);
 
 /* Compress d_src, a row-major (rows, D) array of `dtype` (alignment: the
@@ -118,6 +126,23 @@ spz_status sprintz_get_info(const void *h_src, size_t n, spz_info *out);
  * *d_status; their output rows are then unspecified. */
 spz_status sprintz_decompress(const void *d_src, size_t src_size, const spz_info *info, void *d_dst,
                               size_t dst_cap, int32_t *d_status, hipStream_t stream);
+
+/* Entropy-coded containers (info->params.entropy = 1): bytes of device
+ * workspace sprintz_decompress_ws needs -- a plain container whose segments
+ * sit at a fixed stride (the largest plain segment of the shape). 0 for
+ * plain containers. */
+size_t sprintz_decompress_workspace_size(const spz_info *info);
+
+/* sprintz_decompress with a caller workspace (16-byte aligned, ws_size >=
+ * sprintz_decompress_workspace_size; ignored for plain containers). Each
+ * segment is Huffman-decoded into the workspace (the inverse of Section 4.3's
+ * last stage), then decoded as by sprintz_decompress. A corrupt coded segment
+ * sets bit 2 of *d_status. sprintz_decompress on an entropy-coded container
+ * does the same with a stream-ordered allocation (hipMallocAsync /
+ * hipFreeAsync) of the workspace. Batched plans reject entropy-coded
+ * containers (SPZ_EUNSUPPORTED). */
+spz_status sprintz_decompress_ws(const void *d_src, size_t src_size, const spz_info *info, void *d_dst,
+                                 size_t dst_cap, int32_t *d_status, void *d_ws, size_t ws_size, hipStream_t stream);
 
 /* ---- Batched decompression ------------------------------------------------
  *

@@ -61,6 +61,10 @@ _SIGNATURES = {
     "sprintz_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(spz_info)]),
     "sprintz_decompress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(spz_info),
                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
+    "sprintz_decompress_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(spz_info)]),
+    "sprintz_decompress_ws": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(spz_info),
+                                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_size_t, ctypes.c_void_p]),
     "sprintz_batch_create": (ctypes.c_int, [ctypes.POINTER(spz_batch_item), ctypes.POINTER(spz_info),
                                             ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
     "sprintz_batch_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(spz_batch_item), ctypes.POINTER(spz_info),
@@ -100,12 +104,14 @@ def spz_params_default() -> spz_params:
     return p
 
 
-def make_params(forecaster: str = "fire", seg_rows: int = 1024, hdr_group: int = 0, learn_shift: int = 1) -> spz_params:
+def make_params(forecaster: str = "fire", seg_rows: int = 1024, hdr_group: int = 0, learn_shift: int = 1,
+                entropy: int = 0) -> spz_params:
     p = spz_params_default()
     p.forecaster = FORECASTERS[forecaster]
     p.seg_rows = seg_rows
     p.hdr_group = hdr_group
     p.learn_shift = learn_shift
+    p.entropy = entropy
     return p
 
 
@@ -135,6 +141,16 @@ def sprintz_get_info(h_src: bytes) -> spz_info:
 def sprintz_decompress(d_src: int, src_size: int, info: spz_info, d_dst: int, dst_cap: int, d_status: int,
                        stream: int) -> int:
     return int(load().sprintz_decompress(d_src, src_size, ctypes.byref(info), d_dst, dst_cap, d_status, stream))
+
+
+def sprintz_decompress_workspace_size(info: spz_info) -> int:
+    return int(load().sprintz_decompress_workspace_size(ctypes.byref(info)))
+
+
+def sprintz_decompress_ws(d_src: int, src_size: int, info: spz_info, d_dst: int, dst_cap: int, d_status: int,
+                          d_ws: int, ws_size: int, stream: int) -> int:
+    return int(load().sprintz_decompress_ws(d_src, src_size, ctypes.byref(info), d_dst, dst_cap, d_status, d_ws,
+                                            ws_size, stream))
 
 
 def sprintz_batch_create(items, infos) -> int:
@@ -248,16 +264,17 @@ class Encoder:
 
 
 def compress(x, forecaster: str = "fire", seg_rows: int = 1024, hdr_group: int = 0, learn_shift: int = 1,
-             stream=None):
+             stream=None, entropy: int = 0):
     """Compress a (rows, D) int8/uint8/int16/uint16 CUDA tensor; returns the
-    container as a uint8 CUDA tensor of its exact size (synchronises)."""
+    container as a uint8 CUDA tensor of its exact size (synchronises).
+    ``entropy=1`` adds the Huffman stage."""
     torch = _torch()
     if x.dim() == 1:
         x = x.reshape(-1, 1)
     if x.dim() != 2 or not x.is_cuda:
         raise ValueError("expected a 2-D CUDA tensor")
     x = x.contiguous()
-    p = make_params(forecaster, seg_rows, hdr_group, learn_shift)
+    p = make_params(forecaster, seg_rows, hdr_group, learn_shift, entropy)
     enc = Encoder.create(x.shape[0], x.shape[1], dtype_code(x), p, device=x.device)
     enc.run(x, stream)
     torch.cuda.synchronize(x.device)
@@ -280,8 +297,17 @@ def decompress(container, out=None, stream=None, check: bool = True):
     if out is None:
         out = torch.empty((info.rows, info.D), dtype=torch_dtype(info.dtype), device=container.device)
     status = torch.zeros(1, dtype=torch.int32, device=container.device)
-    rc = sprintz_decompress(container.data_ptr(), container.numel(), info, out.data_ptr(),
-                            out.numel() * out.element_size(), status.data_ptr(), _stream_handle(stream))
+    wsz = sprintz_decompress_workspace_size(info)
+    if wsz:
+        ws = torch.empty(wsz, dtype=torch.uint8, device=container.device)
+        if stream is not None:
+            ws.record_stream(stream)
+        rc = sprintz_decompress_ws(container.data_ptr(), container.numel(), info, out.data_ptr(),
+                                   out.numel() * out.element_size(), status.data_ptr(), ws.data_ptr(), wsz,
+                                   _stream_handle(stream))
+    else:
+        rc = sprintz_decompress(container.data_ptr(), container.numel(), info, out.data_ptr(),
+                                out.numel() * out.element_size(), status.data_ptr(), _stream_handle(stream))
     if rc != SPZ_OK:
         raise SprintzError(rc, "sprintz_decompress")
     if check:

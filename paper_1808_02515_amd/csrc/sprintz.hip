@@ -20,6 +20,7 @@
 #include "spz_decode_pc.h"
 #include "spz_encode.h"
 #include "spz_encode_chunked.h"
+#include "spz_entropy.h"
 
 namespace {
 
@@ -42,12 +43,13 @@ uint32_t log2_pow2_ceil(uint32_t v) {
 }
 
 size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 spz_status check_params(const spz_params *p) {
     if (!p || p->struct_size < sizeof(spz_params)) return SPZ_EINVAL;
     if (p->forecaster != SPZ_DELTA && p->forecaster != SPZ_FIRE) return SPZ_EINVAL;
     if (p->seg_rows < 8 || p->seg_rows % 8 != 0 || p->seg_rows > kMaxSegRows) return SPZ_EINVAL;
-    if (p->hdr_group > 255 || p->learn_shift > 8 || p->entropy != 0) return SPZ_EINVAL;
+    if (p->hdr_group > 255 || p->learn_shift > 8 || p->entropy > 1) return SPZ_EINVAL;
     return SPZ_OK;
 }
 
@@ -174,9 +176,27 @@ void spz_params_default(spz_params *p) {
     p->entropy = 0;
 }
 
+// Largest plain segment of a container shape (16-byte multiple): the
+// decoder's stride for entropy-coded containers.
+static uint64_t plain_segment_max(uint64_t rows, uint32_t D, uint32_t w, const spz_params *p) {
+    const uint32_t hb = w == 8 ? 3 : 4;
+    const uint64_t r = std::min<uint64_t>(rows, p->seg_rows);
+    const uint64_t nblk = r / 8, tail = r % 8;
+    const uint64_t ngroups = p->hdr_group == 0 ? 1 : (nblk + p->hdr_group - 1) / p->hdr_group;
+    const uint64_t one = 4 + (nblk * D * hb + 7) / 8 + ngroups + nblk * D * w + tail * D * (w / 8) + 15;
+    return (one + 15) & ~15ull;
+}
+
+static constexpr uint64_t kHufLdsMax = 60 * 1024;   // coded segment image of the entropy write pass
+
 size_t sprintz_compress_bound(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
     const uint32_t w = bits_of(dtype);
     if (w == 0 || D == 0 || check_params(p) != SPZ_OK) return 0;
+    if (p->entropy == 1) {
+        const uint64_t nseg = num_segments(rows, p->seg_rows);
+        return align16(kHeader + 8 * (size_t)(nseg + 1)) +
+               (size_t)(nseg * spz::huff_segment_bound(plain_segment_max(rows, D, w, p)));
+    }
     const uint32_t hb = w == 8 ? 3 : 4;
     const uint32_t S = p->seg_rows;
     const uint64_t nseg = num_segments(rows, S);
@@ -196,7 +216,47 @@ size_t sprintz_compress_bound(uint64_t rows, uint32_t D, spz_dtype dtype, const 
 
 size_t sprintz_workspace_size(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
     if (bits_of(dtype) == 0 || D == 0 || check_params(p) != SPZ_OK) return 0;
-    return 8 * (size_t)num_segments(rows, p->seg_rows) + 8;
+    const uint64_t nseg = num_segments(rows, p->seg_rows);
+    if (p->entropy == 1) {
+        // plain container | its workspace | per-segment code records | plain size
+        spz_params pp = *p;
+        pp.entropy = 0;
+        return align256(sprintz_compress_bound(rows, D, dtype, &pp)) +
+               align256(sprintz_workspace_size(rows, D, dtype, &pp)) + align256(nseg * spz::kHufInfo) + 256;
+    }
+    return 8 * (size_t)nseg + 8;
+}
+
+// Entropy-coded compression: the plain container into the workspace, then
+// the Huffman size pass, offsets and write pass (Section 4.3's last stage).
+static spz_status compress_entropy(const void *d_src, uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p,
+                            void *d_dst, size_t dst_cap, uint64_t *d_out_size, void *d_ws, int32_t *d_status,
+                            hipStream_t stream) {
+    const uint32_t w = bits_of(dtype);
+    spz_params pp = *p;
+    pp.entropy = 0;
+    const uint64_t nseg = num_segments(rows, p->seg_rows);
+    const uint64_t ldsb = spz::huff_segment_bound(plain_segment_max(rows, D, w, p));
+    if (nseg > 0 && ldsb > kHufLdsMax) return SPZ_EUNSUPPORTED;
+    const size_t plain_cap = sprintz_compress_bound(rows, D, dtype, &pp);
+    const size_t plain_ws = sprintz_workspace_size(rows, D, dtype, &pp);
+    uint8_t *P = (uint8_t *)d_ws;
+    uint8_t *W1 = P + align256(plain_cap);
+    uint8_t *info = W1 + align256(plain_ws);
+    uint64_t *psize = (uint64_t *)(info + align256(nseg * spz::kHufInfo));
+    const spz_status st = sprintz_compress(d_src, rows, D, dtype, &pp, P, plain_cap, psize, W1, plain_ws, d_status,
+                                           stream);
+    if (st != SPZ_OK) return st;
+    const uint64_t data_start = align16(kHeader + 8 * (nseg + 1));
+    if (nseg > 0)
+        hipLaunchKernelGGL(spz::k_huff_size, dim3((uint32_t)nseg), dim3(256), 0, stream, P, data_start, (uint32_t)nseg,
+                           info, d_status);
+    hipLaunchKernelGGL(spz::k_huff_scan, dim3(1), dim3(1024), 0, stream, P, (uint32_t)nseg, data_start, info,
+                       (uint8_t *)d_dst, (uint64_t)dst_cap, d_out_size, d_status);
+    if (nseg > 0)
+        hipLaunchKernelGGL(spz::k_huff_write, dim3((uint32_t)nseg), dim3(256), (uint32_t)ldsb, stream, P, data_start,
+                           (uint32_t)nseg, info, (uint8_t *)d_dst, (uint32_t)ldsb, d_status);
+    return hipGetLastError() == hipSuccess ? SPZ_OK : SPZ_EHIP;
 }
 
 spz_status sprintz_compress(const void *d_src, uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p,
@@ -214,6 +274,8 @@ spz_status sprintz_compress(const void *d_src, uint64_t rows, uint32_t D, spz_dt
         return SPZ_EINVAL;
     if (dst_cap < sprintz_compress_bound(rows, D, dtype, p)) return SPZ_ENOSPC;
     if (ws_size < sprintz_workspace_size(rows, D, dtype, p)) return SPZ_ENOSPC;
+    if (p->entropy == 1) return compress_entropy(d_src, rows, D, dtype, p, d_dst, dst_cap, d_out_size, d_ws, d_status,
+                                                 stream);
     spz::Geom g = make_geom(rows, D, w, p->seg_rows, p->hdr_group, p->learn_shift);
     g.cap = dst_cap;
     const bool col = (uint64_t)D * w <= 32;
@@ -253,7 +315,7 @@ spz_status sprintz_get_info(const void *h_src, size_t n, spz_info *out) {
     info.nseg = (uint32_t)get_le(s + 28, 4);
     const uint64_t data_bytes = get_le(s + 32, 8);
     if (bits_of((spz_dtype)info.dtype) != info.w || info.D == 0) return SPZ_ECORRUPT;
-    if (info.params.forecaster > 1 || info.params.learn_shift > 8 || info.params.entropy != 0) return SPZ_ECORRUPT;
+    if (info.params.forecaster > 1 || info.params.learn_shift > 8 || info.params.entropy > 1) return SPZ_ECORRUPT;
     if (info.params.seg_rows < 8 || info.params.seg_rows % 8 != 0) return SPZ_ECORRUPT;
     if (num_segments(info.rows, info.params.seg_rows) != info.nseg) return SPZ_ECORRUPT;
     info.compressed_size = align16(kHeader + 8ull * (info.nseg + 1)) + data_bytes;
@@ -363,12 +425,52 @@ struct spz_batch {
 
 extern "C" {
 
+size_t sprintz_decompress_workspace_size(const spz_info *info) {
+    if (!info || info->params.entropy != 1 || (info->w != 8 && info->w != 16)) return 0;
+    return align16(kHeader + 8 * (size_t)(info->nseg + 1)) +
+           (size_t)(info->nseg * plain_segment_max(info->rows, info->D, info->w, &info->params));
+}
+
+spz_status sprintz_decompress_ws(const void *d_src, size_t src_size, const spz_info *info, void *d_dst,
+                                 size_t dst_cap, int32_t *d_status, void *d_ws, size_t ws_size, hipStream_t stream) {
+    spz::Geom g;
+    const spz_status st = check_decompress(d_src, src_size, info, d_dst, dst_cap, &g);
+    if (st != SPZ_OK) return st;
+    if (info->params.entropy == 0) return launch_decode_any(d_src, info, g, d_dst, d_status, stream) == hipSuccess ? SPZ_OK : SPZ_EHIP;
+    if (!d_ws || ((uintptr_t)d_ws & 15) || ws_size < sprintz_decompress_workspace_size(info)) return SPZ_ENOSPC;
+    if (info->nseg == 0) return SPZ_OK;
+    // Huffman-decode every segment into a plain container at a fixed
+    // segment stride, then decode that container
+    const uint64_t stride = plain_segment_max(info->rows, info->D, info->w, &info->params);
+    uint8_t *ws = (uint8_t *)d_ws;
+    hipLaunchKernelGGL(spz::k_huff_plain_table, dim3((info->nseg + 1 + 255) / 256), dim3(256), 0, stream,
+                       (const uint8_t *)d_src, info->nseg, stride, ws);
+    hipLaunchKernelGGL(spz::k_huff_decode, dim3((info->nseg + spz::kHufSegsPerWave - 1) / spz::kHufSegsPerWave),
+                       dim3(64), 0, stream, (const uint8_t *)d_src, (uint64_t)src_size, g.data_start, g.data_bytes,
+                       info->nseg, ws, stride, d_status);
+    spz_info pi = *info;
+    pi.params.entropy = 0;
+    pi.compressed_size = g.data_start + stride * info->nseg;
+    spz::Geom pg = g;
+    pg.cap = ws_size;
+    pg.data_bytes = stride * info->nseg;
+    return launch_decode_any(ws, &pi, pg, d_dst, d_status, stream) == hipSuccess ? SPZ_OK : SPZ_EHIP;
+}
+
 spz_status sprintz_decompress(const void *d_src, size_t src_size, const spz_info *info, void *d_dst,
                               size_t dst_cap, int32_t *d_status, hipStream_t stream) {
     spz::Geom g;
     const spz_status st = check_decompress(d_src, src_size, info, d_dst, dst_cap, &g);
     if (st != SPZ_OK) return st;
-    return launch_decode_any(d_src, info, g, d_dst, d_status, stream) == hipSuccess ? SPZ_OK : SPZ_EHIP;
+    if (info->params.entropy == 0)
+        return launch_decode_any(d_src, info, g, d_dst, d_status, stream) == hipSuccess ? SPZ_OK : SPZ_EHIP;
+    // entropy-coded: a stream-ordered workspace for the plain container
+    const size_t wsz = sprintz_decompress_workspace_size(info);
+    void *ws = nullptr;
+    if (hipMallocAsync(&ws, wsz, stream) != hipSuccess) return SPZ_ENOMEM;
+    const spz_status r = sprintz_decompress_ws(d_src, src_size, info, d_dst, dst_cap, d_status, ws, wsz, stream);
+    if (hipFreeAsync(ws, stream) != hipSuccess) return SPZ_EHIP;
+    return r;
 }
 
 }  // extern "C"
@@ -386,6 +488,7 @@ spz_status build_plan(const spz_batch_item *items, const spz_info *infos, uint32
             check_decompress(items[i].d_src, items[i].src_size, &infos[i], items[i].d_dst, items[i].dst_cap, &geoms[i]);
         if (st != SPZ_OK) return st;
         const spz_info &in = infos[i];
+        if (in.params.entropy != 0) return SPZ_EUNSUPPORTED;
         const uint32_t D = in.D;
         if (D >= 1 && D <= 16 && in.params.hdr_group == 0 && !((uintptr_t)items[i].d_dst & 15) &&
             ((uint64_t)in.params.seg_rows * D * (in.w / 8)) % 16 == 0 && in.nseg > 0)

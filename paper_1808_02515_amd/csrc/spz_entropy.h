@@ -1,0 +1,448 @@
+// Entropy stage of the gfx950 Sprintz codec: Huffman coding of every
+// segment's packed bytes.
+//
+// Paper: Section 4.3 closes the pipeline with a byte-oriented Huffman coder
+// run over the bit-packed headers and payloads (bytes are the symbols,
+// whatever the data's bit width). The coder and its byte format are this
+// library's own (the paper uses an external coder):
+//   - one code per segment, from the byte counts of the plain segment;
+//   - code lengths by the two-queue Huffman construction over the present
+//     byte values in (count, value) order, a leaf taken before an internal
+//     node of equal weight; if a length exceeds 11 bits every count c becomes
+//     (c + 1) / 2 and the construction runs again; a lone value gets length 1;
+//   - canonical codes in (length, value) order;
+//   - 16 sub-streams per segment, sub-stream k coding plain bytes
+//     [k n/16, (k+1) n/16) as a byte-aligned LSB-first bit string, every code
+//     stored from its first (most significant) bit on.
+// Coded segment: u32 n | u8 len[128] (4 bits per value, even values low) |
+// u32 size[16] | the 16 sub-streams | zero pad to 16 bytes.
+//
+// Compression runs the plain encoder into a workspace container, then
+//   k_huff_size   one workgroup per segment: byte histograms (one per
+//                 sub-stream), code lengths, coded size
+//   k_huff_scan   offsets of the coded segments, container header
+//   k_huff_write  one workgroup per segment: canonical codes, every byte's
+//                 code OR-ed into an LDS image of the coded segment at its
+//                 bit offset (scans over the byte ranges), 16-byte stores.
+// Decompression runs
+//   k_huff_decode one wavefront per four segments, 16 lanes per segment: a
+//                 2048-entry table (11-bit lookup) per segment in LDS, one
+//                 sub-stream per lane read with aligned 16-byte loads kept
+//                 four blocks ahead, plain bytes stored at a fixed stride
+//   k_huff_plain_table  the workspace container's header and offset table,
+// and then the plain decoder over the workspace container.
+#pragma once
+
+#include "spz_device.h"
+
+namespace spz {
+
+constexpr uint32_t kHufMaxLen = 11;
+constexpr uint32_t kHufSub = 16;
+constexpr uint32_t kHufFixed = 4 + 128 + 4 * kHufSub;   // n, lengths, sub-stream sizes
+constexpr uint32_t kHufInfo = 256;                      // per-segment record in the encoder workspace
+constexpr uint32_t kHufSegsPerWave = 4;                 // decoder: segments per wavefront
+
+// Upper bound of a coded segment for a plain segment of n bytes.
+__host__ __device__ inline uint64_t huff_segment_bound(uint64_t n) {
+    return (kHufFixed + (n * kHufMaxLen + 7) / 8 + kHufSub + 15) & ~15ull;
+}
+
+__device__ __forceinline__ uint32_t huff_rev(uint32_t code, uint32_t len) {
+    return __builtin_bitreverse32(code) >> (32 - len);
+}
+
+// ---- size pass -----------------------------------------------------------
+// plain: plain container (offset table at +64, data at +data_start); info:
+// kHufInfo bytes per segment: len nibbles [0,128), sub-stream bytes
+// [128,192), coded segment bytes at 192.
+__global__ __launch_bounds__(256) void k_huff_size(const uint8_t *__restrict__ plain, uint64_t data_start,
+                                                   uint32_t nseg, uint8_t *__restrict__ info,
+                                                   int32_t *__restrict__ status) {
+    __shared__ uint32_t hist[kHufSub][256];
+    __shared__ uint32_t f[256];
+    __shared__ uint32_t order[256];
+    __shared__ uint32_t weight[512];
+    __shared__ uint32_t parent[512];
+    __shared__ uint32_t len[256];
+    __shared__ uint32_t sub_bits[kHufSub];
+    __shared__ uint32_t nsym, maxlen;
+    const uint32_t t = threadIdx.x, s = blockIdx.x;
+    if (s >= nseg) return;
+    const uint64_t a = gld64(plain + 64 + 8ull * s), b = gld64(plain + 64 + 8ull * (s + 1));
+    const uint8_t *seg = plain + data_start + a;
+    const uint32_t n = (uint32_t)(b - a);
+    const uint32_t m16 = n / kHufSub;
+    for (uint32_t k = t; k < kHufSub * 256; k += 256) (&hist[0][0])[k] = 0;
+    if (t < kHufSub) sub_bits[t] = 0;
+    __syncthreads();
+    // byte histograms per sub-stream (16-byte loads)
+    for (uint32_t q = t; q < n / 16; q += 256) {
+        const u32x4 v = gld128(seg + 16 * q);
+        const uint32_t wds[4] = {v.x, v.y, v.z, v.w};
+        uint32_t pos = 16 * q, k = pos / m16;
+#pragma unroll
+        for (int i = 0; i < 16; ++i, ++pos) {
+            while (pos >= (k + 1) * m16) ++k;
+            atomicAdd(&hist[k][(wds[i >> 2] >> (8 * (i & 3))) & 0xFFu], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kHufSub; ++k) c += hist[k][t];
+    f[t] = c;
+    // code lengths: two-queue construction, repeated on halved counts while
+    // a length exceeds the limit
+    for (;;) {
+        if (t == 0) { nsym = 0; maxlen = 0; }
+        __syncthreads();
+        const uint32_t fv = f[t];
+        uint32_t rank = 0;
+        if (fv) {
+            for (uint32_t u = 0; u < 256; ++u) {
+                const uint32_t fu = f[u];
+                rank += (fu != 0 && (fu < fv || (fu == fv && u < t))) ? 1u : 0u;
+            }
+            order[rank] = t;
+            atomicAdd(&nsym, 1u);
+        }
+        __syncthreads();
+        const uint32_t m = nsym;
+        if (m == 1) {
+            len[t] = fv ? 1u : 0u;
+            __syncthreads();
+            break;
+        }
+        if (t == 0) {
+            for (uint32_t k = 0; k < m; ++k) weight[k] = f[order[k]];
+            uint32_t leaf = 0, inner = m, next = m;
+            for (uint32_t step = 0; step + 1 < m; ++step) {
+                uint32_t pick[2];
+                for (int q = 0; q < 2; ++q) {
+                    const bool use_leaf = leaf < m && (inner >= next || weight[leaf] <= weight[inner]);
+                    pick[q] = use_leaf ? leaf++ : inner++;
+                }
+                weight[next] = weight[pick[0]] + weight[pick[1]];
+                parent[pick[0]] = next;
+                parent[pick[1]] = next;
+                ++next;
+            }
+        }
+        __syncthreads();
+        uint32_t d = 0;
+        if (fv) {
+            const uint32_t root = 2 * m - 2;
+            for (uint32_t q = rank; q != root; q = parent[q]) ++d;
+            atomicMax(&maxlen, d);
+        }
+        len[t] = d;
+        __syncthreads();
+        if (maxlen <= kHufMaxLen) break;
+        f[t] = (fv + 1) >> 1;
+        __syncthreads();
+    }
+    // bits of every sub-stream: sum over values of count * length
+    {
+        const uint32_t k = t >> 4, v0 = (t & 15) * 16;
+        uint32_t bits = 0;
+        for (uint32_t v = v0; v < v0 + 16; ++v) bits += hist[k][v] * len[v];
+        atomicAdd(&sub_bits[k], bits);
+    }
+    __syncthreads();
+    uint8_t *rec = info + (uint64_t)s * kHufInfo;
+    if (t < 128) rec[t] = (uint8_t)(len[2 * t] | (len[2 * t + 1] << 4));
+    if (t < kHufSub) reinterpret_cast<uint32_t *>(rec + 128)[t] = (sub_bits[t] + 7) >> 3;
+    if (t == 0) {
+        uint32_t tot = kHufFixed;
+        for (uint32_t k = 0; k < kHufSub; ++k) tot += (sub_bits[k] + 7) >> 3;
+        reinterpret_cast<uint32_t *>(rec + 192)[0] = (tot + 15) & ~15u;
+        if ((n % 16 || n == 0) && status) atomicOr(status, 2);
+    }
+}
+
+// ---- offsets and header --------------------------------------------------
+__global__ __launch_bounds__(1024) void k_huff_scan(const uint8_t *__restrict__ plain, uint32_t nseg,
+                                                    uint64_t data_start, const uint8_t *__restrict__ info,
+                                                    uint8_t *__restrict__ dst, uint64_t cap,
+                                                    uint64_t *__restrict__ out_size, int32_t *__restrict__ status) {
+    __shared__ uint64_t wsum[16];
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint64_t *tab = reinterpret_cast<uint64_t *>(dst + 64);
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < nseg; base += 1024) {
+        const uint32_t k = base + t;
+        const uint32_t v = k < nseg ? reinterpret_cast<const uint32_t *>(info + (uint64_t)k * kHufInfo + 192)[0] : 0u;
+        uint64_t incl = v;
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint64_t o = (uint64_t)__shfl_up((unsigned long long)incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        uint64_t before = carry, total = carry;
+        for (uint32_t q = 0; q < 16; ++q) {
+            const uint64_t ws = wsum[q];
+            if (q < wv) before += ws;
+            total += ws;
+        }
+        if (k < nseg) tab[k] = before + incl - v;
+        carry = total;
+        __syncthreads();
+    }
+    if (t == 0) tab[nseg] = carry;
+    if (t < 16) {
+        // the plain header with entropy 1 and the coded data size
+        uint32_t word = reinterpret_cast<const uint32_t *>(plain)[t];
+        if (t == 2) word = (word & 0x00FFFFFFu) | (1u << 24);
+        if (t == 8) word = (uint32_t)carry;
+        if (t == 9) word = (uint32_t)(carry >> 32);
+        reinterpret_cast<uint32_t *>(dst)[t] = word;
+    }
+    const uint64_t pad0 = 64 + 8ull * (nseg + 1);
+    if (t < data_start - pad0) dst[pad0 + t] = 0;
+    if (t == 0) {
+        *out_size = data_start + carry;
+        if (data_start + carry > cap && status) atomicOr(status, 2);
+    }
+}
+
+// ---- write pass ----------------------------------------------------------
+// Dynamic LDS: the coded segment image (ldsb bytes, a multiple of 16).
+__global__ __launch_bounds__(256) void k_huff_write(const uint8_t *__restrict__ plain, uint64_t data_start,
+                                                    uint32_t nseg, const uint8_t *__restrict__ info,
+                                                    uint8_t *__restrict__ dst, uint32_t ldsb,
+                                                    int32_t *__restrict__ status) {
+    extern __shared__ u32x4 img4[];
+    __shared__ uint32_t len[256], rcode[256], cntl[kHufMaxLen + 1], first[kHufMaxLen + 1];
+    __shared__ uint32_t sub_base[kHufSub];
+    uint32_t *img = reinterpret_cast<uint32_t *>(img4);
+    const uint32_t t = threadIdx.x, s = blockIdx.x;
+    if (s >= nseg) return;
+    const uint64_t a = gld64(plain + 64 + 8ull * s), b = gld64(plain + 64 + 8ull * (s + 1));
+    const uint8_t *seg = plain + data_start + a;
+    const uint32_t n = (uint32_t)(b - a), m16 = n / kHufSub;
+    const uint8_t *rec = info + (uint64_t)s * kHufInfo;
+    const uint32_t coded = reinterpret_cast<const uint32_t *>(rec + 192)[0];
+    if (coded > ldsb) {
+        if (t == 0 && status) atomicOr(status, 2);
+        return;
+    }
+    for (uint32_t k = t; k < coded / 4; k += 256) img[k] = 0;
+    const uint32_t lv = (gld8(rec + (t >> 1)) >> (4 * (t & 1))) & 15u;
+    len[t] = lv;
+    if (t <= kHufMaxLen) cntl[t] = 0;
+    __syncthreads();
+    if (lv) atomicAdd(&cntl[lv], 1u);
+    if (t < kHufSub) {
+        uint32_t base = kHufFixed;
+        for (uint32_t k = 0; k < t; ++k) base += reinterpret_cast<const uint32_t *>(rec + 128)[k];
+        sub_base[t] = base;
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t c = 0;
+        for (uint32_t l = 1; l <= kHufMaxLen; ++l) {
+            first[l] = c;
+            c = (c + cntl[l]) << 1;
+        }
+    }
+    __syncthreads();
+    {
+        uint32_t r = 0;
+        for (uint32_t u = 0; u < t; ++u) r += len[u] == lv ? 1u : 0u;
+        rcode[t] = lv ? huff_rev(first[lv] + r, lv) : 0u;
+    }
+    // fixed part: n, lengths, sub-stream sizes (bytes 0..195; streams start at 196)
+    if (t < 49) {
+        uint32_t word;
+        if (t == 0) word = n;
+        else if (t <= 32) word = gld32(rec + 4 * (t - 1));
+        else word = reinterpret_cast<const uint32_t *>(rec + 128)[t - 33];
+        img[t] = word;
+    }
+    __syncthreads();
+    // thread = (sub-stream k, part p): bit offsets by a scan over the parts
+    const uint32_t k = t >> 4, p = t & 15;
+    const uint32_t q = (m16 + 15) / 16;
+    const uint32_t lo = min(p * q, m16), hi = min(lo + q, m16);
+    const uint8_t *src = seg + k * m16;
+    uint32_t bits = 0;
+    for (uint32_t i = lo; i < hi; ++i) bits += len[gld8(src + i)];
+    uint32_t incl = bits;
+#pragma unroll
+    for (uint32_t d = 1; d < 16; d <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_up((int)incl, d, 16);
+        if (p >= d) incl += o;
+    }
+    uint32_t pos = 8 * sub_base[k] + incl - bits;
+    for (uint32_t i = lo; i < hi; ++i) {
+        const uint32_t v = gld8(src + i);
+        const uint32_t l = len[v], rc = rcode[v];
+        atomicOr(&img[pos >> 5], rc << (pos & 31));
+        if ((pos & 31) + l > 32) atomicOr(&img[(pos >> 5) + 1], rc >> (32 - (pos & 31)));
+        pos += l;
+    }
+    __syncthreads();
+    const uint64_t ta = gld64(dst + 64 + 8ull * s);
+    uint8_t *out = dst + data_start + ta;
+    for (uint32_t u = t; u < coded / 16; u += 256) gst128(out + 16 * u, img4[u]);
+}
+
+// ---- decode --------------------------------------------------------------
+// Lanes (segment g of the wavefront's four, sub-stream k). Plain segment s
+// goes to plain + data_start + s * stride.
+__global__ __launch_bounds__(64) void k_huff_decode(const uint8_t *__restrict__ src, uint64_t src_size,
+                                                    uint64_t data_start, uint64_t data_bytes, uint32_t nseg,
+                                                    uint8_t *__restrict__ plain, uint64_t stride,
+                                                    int32_t *__restrict__ status) {
+    __shared__ uint16_t lut[kHufSegsPerWave][1u << kHufMaxLen];
+    __shared__ uint32_t cnt[kHufSegsPerWave][kHufSub][kHufMaxLen + 1];
+    __shared__ uint32_t first[kHufSegsPerWave][kHufMaxLen + 1];
+    const uint32_t lane = threadIdx.x, g = lane >> 4, k = lane & 15;
+    const uint32_t s = blockIdx.x * kHufSegsPerWave + g;
+    bool ok = s < nseg;
+    uint64_t a = 0, b = 0;
+    if (ok) {
+        a = gld64(src + 64 + 8ull * s);
+        b = gld64(src + 64 + 8ull * (s + 1));
+        ok = a <= b && b <= data_bytes && !((a | b) & 15u) && b - a >= kHufFixed && data_start + b <= src_size;
+    }
+    const uint8_t *seg = src + data_start + a;
+    const uint32_t n = ok ? gld32(seg) : 0u;
+    if (ok && (n % 16 || n == 0 || n > stride)) ok = false;
+    // this lane's 16 values: lengths, counts per length
+    uint32_t lw[2] = {0u, 0u};
+    if (ok) { lw[0] = gld32(seg + 4 + 8 * k); lw[1] = gld32(seg + 8 + 8 * k); }
+    uint32_t lc[kHufMaxLen + 1];
+#pragma unroll
+    for (uint32_t l = 0; l <= kHufMaxLen; ++l) lc[l] = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 16; ++i) {
+        const uint32_t l = (lw[i >> 3] >> (4 * (i & 7))) & 15u;
+#pragma unroll
+        for (uint32_t q = 1; q <= kHufMaxLen; ++q) lc[q] += l == q ? 1u : 0u;
+        if (l > kHufMaxLen) ok = false;
+    }
+#pragma unroll
+    for (uint32_t l = 0; l <= kHufMaxLen; ++l) cnt[g][k][l] = lc[l];
+    wave_sync();
+    if (k == 0) {
+        uint32_t c = 0;
+        for (uint32_t l = 1; l <= kHufMaxLen; ++l) {
+            first[g][l] = c;
+            uint32_t tot = 0;
+            for (uint32_t q = 0; q < kHufSub; ++q) tot += cnt[g][q][l];
+            c = (c + tot) << 1;
+        }
+    }
+    for (uint32_t e = k; e < (1u << kHufMaxLen); e += kHufSub) lut[g][e] = 0;
+    wave_sync();
+    // canonical code of each value: first code of its length + values of that
+    // length before it (earlier lanes, then earlier values of this lane)
+    uint32_t seen[kHufMaxLen + 1];
+#pragma unroll
+    for (uint32_t l = 1; l <= kHufMaxLen; ++l) {
+        uint32_t before = 0;
+        for (uint32_t q = 0; q < k; ++q) before += cnt[g][q][l];
+        seen[l] = first[g][l] + before;
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < 16; ++i) {
+        const uint32_t l = (lw[i >> 3] >> (4 * (i & 7))) & 15u;
+        if (l == 0 || l > kHufMaxLen) continue;
+        uint32_t code = 0;
+#pragma unroll
+        for (uint32_t q = 1; q <= kHufMaxLen; ++q)
+            if (q == l) { code = seen[q]; seen[q] = code + 1; }
+        if (code >= (1u << l)) { ok = false; continue; }
+        const uint32_t r = huff_rev(code, l);
+        const uint16_t e = (uint16_t)((16 * k + i) | (l << 8));
+        for (uint32_t j = 0; j < (1u << (kHufMaxLen - l)); ++j) lut[g][r | (j << l)] = e;
+    }
+    wave_sync();
+    // this lane's sub-stream
+    uint32_t size = ok ? gld32(seg + 132 + 4 * k) : 0u;
+    uint32_t incl = size;
+#pragma unroll
+    for (uint32_t d = 1; d < 16; d <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_up((int)incl, d, 16);
+        if (k >= d) incl += o;
+    }
+    const uint64_t sbeg = a + kHufFixed + incl - size;   // data-relative byte offset
+    if (ok && sbeg + size > b) ok = false;
+    const uint32_t m16 = n / kHufSub;
+    const uint32_t count = ok ? m16 : 0u;
+    uint8_t *out = plain + data_start + (uint64_t)s * stride + (uint64_t)k * m16;
+    // aligned 16-byte blocks of the sub-stream, four in flight
+    const uint8_t *data = src + data_start;
+    uint64_t blk = sbeg & ~15ull;
+    auto load = [&](uint64_t off) -> u32x4 {
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (ok && off + 16 <= data_bytes) v = gld128(data + off);
+        return v;
+    };
+    u32x4 q0 = load(blk), q1 = load(blk + 16), q2 = load(blk + 32), q3 = load(blk + 48);
+    blk += 64;
+    uint32_t wi = (uint32_t)(sbeg & 15) >> 2;     // next word of q0
+    uint64_t bb = 0;
+    uint32_t nb = 0;
+    auto refill = [&]() {
+        const uint32_t wd = wi == 0 ? q0.x : wi == 1 ? q0.y : wi == 2 ? q0.z : q0.w;
+        bb |= (uint64_t)wd << nb;
+        nb += 32;
+        if (++wi == 4) {
+            q0 = q1; q1 = q2; q2 = q3; q3 = load(blk);
+            blk += 16;
+            wi = 0;
+        }
+    };
+    refill();
+    refill();
+    {
+        const uint32_t skip = 8 * ((uint32_t)sbeg & 3);
+        bb >>= skip;
+        nb -= skip;
+    }
+    uint32_t acc = 0, bad = 0;
+    uint64_t used = 0;
+    const bool out4 = ((uintptr_t)out & 3) == 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (nb < 32) refill();
+        const uint32_t e = lut[g][(uint32_t)bb & ((1u << kHufMaxLen) - 1)];
+        const uint32_t l = e >> 8;
+        bad |= l == 0 ? 1u : 0u;
+        bb >>= l;
+        nb -= l;
+        used += l;
+        acc |= (e & 0xFFu) << (8 * (i & 3));
+        if ((i & 3) == 3 || i + 1 == count) {
+            // bytes i - (i & 3) .. i of this lane's range
+            const uint32_t i0 = i & ~3u;
+            if (out4 && i == i0 + 3) {
+                gst32(out + i0, acc);
+            } else {
+                for (uint32_t t = i0; t <= i; ++t) gst8(out + t, acc >> (8 * (t - i0)));
+            }
+            acc = 0;
+        }
+    }
+    if (bad || used > 8ull * size) ok = false;
+    if (s < nseg && !ok && status) atomicOr(status, 4);
+}
+
+// Header and offset table of the workspace (plain) container.
+__global__ void k_huff_plain_table(const uint8_t *__restrict__ src, uint32_t nseg, uint64_t stride,
+                                   uint8_t *__restrict__ plain) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 16) {
+        uint32_t word = gld32(src + 4 * t);
+        if (t == 2) word &= 0x00FFFFFFu;   // entropy 0
+        if (t == 8) word = (uint32_t)(stride * nseg);
+        if (t == 9) word = (uint32_t)((stride * nseg) >> 32);
+        reinterpret_cast<uint32_t *>(plain)[t] = word;
+    }
+    if (t <= nseg) reinterpret_cast<uint64_t *>(plain + 64)[t] = (uint64_t)t * stride;
+}
+
+}  // namespace spz
