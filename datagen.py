@@ -231,6 +231,32 @@ def ar2_uint16_torch(rows: int, D: int, sigma: float, flat_frac: float, gen, dev
     return x.to(torch.int16).contiguous()   # uint16 bit patterns
 
 
+def wrap_walk_torch(steps, start: int = 32768):
+    """x_t = (start + steps_0 + ... + steps_t) mod 2^16 per column, as int16
+    bit patterns (the wrapping random walk of the entropy workload)."""
+    import torch
+    x = torch.cumsum(steps.to(torch.int64), dim=0) + start
+    return torch.remainder(x, 65536).to(torch.int32).to(torch.int16)
+
+
+def laplace_walk_uint16_torch(rows: int, D: int, scale: float, gen, device, chunk: int = 1 << 25):
+    """``laplace_walk_uint16`` drawn on the GPU in row chunks: steps
+    rint(Laplace(0, scale)) by the inverse CDF of a uniform draw, wrapped
+    walks from 32768 (scans run column by column along contiguous memory).
+    Returns int16 bit patterns."""
+    import torch
+    out = torch.empty((rows, D), dtype=torch.int16, device=device)
+    carry = torch.full((D, 1), 32768, dtype=torch.int64, device=device)
+    for r0 in range(0, rows, chunk):
+        n = min(chunk, rows - r0)
+        u = torch.rand((D, n), generator=gen, device=device, dtype=torch.float64) - 0.5
+        inc = torch.round(-scale * torch.sign(u) * torch.log1p(-2.0 * u.abs())).to(torch.int64)
+        x = torch.cumsum(inc, dim=1) + carry
+        out[r0:r0 + n] = torch.remainder(x, 65536).to(torch.int32).to(torch.int16).t()
+        carry = x[:, -1:].clone()
+    return out
+
+
 def batch_stream_torch(k: int, device="cuda"):
     """Stream k of the batch workload drawn on the GPU (same rows, D, dtype
     and sigma as ``batch_stream_params(k)``); uint16 streams come back as

@@ -60,9 +60,8 @@ __global__ __launch_bounds__(256) void k_huff_size(const uint8_t *__restrict__ p
                                                    uint32_t nseg, uint8_t *__restrict__ info,
                                                    int32_t *__restrict__ status) {
     __shared__ uint32_t hist[kHufSub][256];
-    __shared__ uint32_t f[256];
+    __shared__ u32x4 f4[64];                     // counts, four per entry
     __shared__ uint32_t order[256];
-    __shared__ uint32_t weight[512];
     __shared__ uint32_t parent[512];
     __shared__ uint32_t len[256];
     __shared__ uint32_t sub_bits[kHufSub];
@@ -91,6 +90,7 @@ __global__ __launch_bounds__(256) void k_huff_size(const uint8_t *__restrict__ p
     uint32_t c = 0;
 #pragma unroll
     for (uint32_t k = 0; k < kHufSub; ++k) c += hist[k][t];
+    uint32_t *const f = reinterpret_cast<uint32_t *>(f4);
     f[t] = c;
     // code lengths: two-queue construction, repeated on halved counts while
     // a length exceeds the limit
@@ -100,9 +100,16 @@ __global__ __launch_bounds__(256) void k_huff_size(const uint8_t *__restrict__ p
         const uint32_t fv = f[t];
         uint32_t rank = 0;
         if (fv) {
-            for (uint32_t u = 0; u < 256; ++u) {
-                const uint32_t fu = f[u];
-                rank += (fu != 0 && (fu < fv || (fu == fv && u < t))) ? 1u : 0u;
+            // rank by (count, value): 16-byte reads, 8 in flight
+#pragma unroll 8
+            for (uint32_t u4 = 0; u4 < 64; ++u4) {
+                const u32x4 v = f4[u4];
+                const uint32_t fu[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (uint32_t q = 0; q < 4; ++q) {
+                    const uint32_t u = 4 * u4 + q;
+                    rank += (fu[q] != 0 && (fu[q] < fv || (fu[q] == fv && u < t))) ? 1u : 0u;
+                }
             }
             order[rank] = t;
             atomicAdd(&nsym, 1u);
@@ -114,19 +121,39 @@ __global__ __launch_bounds__(256) void k_huff_size(const uint8_t *__restrict__ p
             __syncthreads();
             break;
         }
-        if (t == 0) {
-            for (uint32_t k = 0; k < m; ++k) weight[k] = f[order[k]];
-            uint32_t leaf = 0, inner = m, next = m;
+        if (t < 64) {
+            // the merge runs in wavefront 0 with the weights in registers:
+            // node i of a queue sits in lane i % 64 of slot i / 64, read with
+            // readlane and written with a lane select, under uniform control
+            uint32_t lw[4], iw[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q) lw[q] = 64 * q + t < m ? f[order[64 * q + t]] : 0u;
+            auto rd = [](const uint32_t (&A)[4], uint32_t i) -> uint32_t {
+                const uint32_t sl = i >> 6;
+                const uint32_t v = sl == 0 ? A[0] : sl == 1 ? A[1] : sl == 2 ? A[2] : A[3];
+                return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(i & 63));
+            };
+            uint32_t leaf = 0, inner = 0, nint = 0;
             for (uint32_t step = 0; step + 1 < m; ++step) {
-                uint32_t pick[2];
+                uint32_t node[2], wsum = 0;
+#pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    const bool use_leaf = leaf < m && (inner >= next || weight[leaf] <= weight[inner]);
-                    pick[q] = use_leaf ? leaf++ : inner++;
+                    const bool has_leaf = leaf < m, has_inner = inner < nint;
+                    const uint32_t a_w = has_leaf ? rd(lw, leaf) : 0u;
+                    const uint32_t b_w = has_inner ? rd(iw, inner) : 0u;
+                    const bool use_leaf = has_leaf && (!has_inner || a_w <= b_w);
+                    node[q] = use_leaf ? leaf : m + inner;
+                    wsum += use_leaf ? a_w : b_w;
+                    if (use_leaf) ++leaf; else ++inner;
                 }
-                weight[next] = weight[pick[0]] + weight[pick[1]];
-                parent[pick[0]] = next;
-                parent[pick[1]] = next;
-                ++next;
+                const uint32_t sl = nint >> 6, ln = nint & 63;
+#pragma unroll
+                for (uint32_t q = 0; q < 4; ++q) iw[q] = (sl == q && t == ln) ? wsum : iw[q];
+                if (t == 0) {
+                    parent[node[0]] = m + nint;
+                    parent[node[1]] = m + nint;
+                }
+                ++nint;
             }
         }
         __syncthreads();
@@ -299,6 +326,9 @@ __global__ __launch_bounds__(64) void k_huff_decode(const uint8_t *__restrict__ 
     __shared__ uint16_t lut[kHufSegsPerWave][1u << kHufMaxLen];
     __shared__ uint32_t cnt[kHufSegsPerWave][kHufSub][kHufMaxLen + 1];
     __shared__ uint32_t first[kHufSegsPerWave][kHufMaxLen + 1];
+    __shared__ uint32_t index[kHufSegsPerWave][kHufMaxLen + 1];   // first position of each length in code order
+    __shared__ uint32_t codes_end[kHufSegsPerWave];              // end of the used 11-bit code space
+    __shared__ uint8_t sorted[kHufSegsPerWave][256];             // values in (length, value) order
     const uint32_t lane = threadIdx.x, g = lane >> 4, k = lane & 15;
     const uint32_t s = blockIdx.x * kHufSegsPerWave + g;
     bool ok = s < nseg;
@@ -328,15 +358,18 @@ __global__ __launch_bounds__(64) void k_huff_decode(const uint8_t *__restrict__ 
     for (uint32_t l = 0; l <= kHufMaxLen; ++l) cnt[g][k][l] = lc[l];
     wave_sync();
     if (k == 0) {
-        uint32_t c = 0;
+        uint32_t c = 0, pos = 0, end = 0;
         for (uint32_t l = 1; l <= kHufMaxLen; ++l) {
             first[g][l] = c;
+            index[g][l] = pos;
             uint32_t tot = 0;
             for (uint32_t q = 0; q < kHufSub; ++q) tot += cnt[g][q][l];
+            if (tot) end = (c + tot) << (kHufMaxLen - l);
+            pos += tot;
             c = (c + tot) << 1;
         }
+        codes_end[g] = end;
     }
-    for (uint32_t e = k; e < (1u << kHufMaxLen); e += kHufSub) lut[g][e] = 0;
     wave_sync();
     // canonical code of each value: first code of its length + values of that
     // length before it (earlier lanes, then earlier values of this lane)
@@ -356,9 +389,33 @@ __global__ __launch_bounds__(64) void k_huff_decode(const uint8_t *__restrict__ 
         for (uint32_t q = 1; q <= kHufMaxLen; ++q)
             if (q == l) { code = seen[q]; seen[q] = code + 1; }
         if (code >= (1u << l)) { ok = false; continue; }
-        const uint32_t r = huff_rev(code, l);
-        const uint16_t e = (uint16_t)((16 * k + i) | (l << 8));
-        for (uint32_t j = 0; j < (1u << (kHufMaxLen - l)); ++j) lut[g][r | (j << l)] = e;
+        sorted[g][(index[g][l] + code - first[g][l]) & 255u] = (uint8_t)(16 * k + i);
+    }
+    wave_sync();
+    // table entries: an 11-bit window (first code bit lowest) read most
+    // significant bit first falls in the left-aligned range of exactly one
+    // code length; the value is found by its offset in that range
+    {
+        uint32_t lj[kHufMaxLen + 1], ix[kHufMaxLen + 1];
+#pragma unroll
+        for (uint32_t l = 1; l <= kHufMaxLen; ++l) {
+            lj[l] = first[g][l] << (kHufMaxLen - l);
+            ix[l] = index[g][l];
+        }
+        const uint32_t end = codes_end[g];
+        for (uint32_t e = k; e < (1u << kHufMaxLen); e += kHufSub) {
+            const uint32_t M = __builtin_bitreverse32(e) >> (32 - kHufMaxLen);
+            uint32_t len_of = 0, base = 0, off = 0;
+#pragma unroll
+            for (uint32_t l = 1; l <= kHufMaxLen; ++l) {
+                // the range of length l is [lj[l], lj[l+1]); an empty length
+                // starts where the next one does, so the last start <= M wins
+                if (M >= lj[l]) { len_of = l; base = ix[l]; off = (M - lj[l]) >> (kHufMaxLen - l); }
+            }
+            uint16_t v = 0;
+            if (M < end && len_of) v = (uint16_t)(sorted[g][(base + off) & 255u] | (len_of << 8));
+            lut[g][e] = v;
+        }
     }
     wave_sync();
     // this lane's sub-stream
@@ -374,60 +431,76 @@ __global__ __launch_bounds__(64) void k_huff_decode(const uint8_t *__restrict__ 
     const uint32_t m16 = n / kHufSub;
     const uint32_t count = ok ? m16 : 0u;
     uint8_t *out = plain + data_start + (uint64_t)s * stride + (uint64_t)k * m16;
-    // aligned 16-byte blocks of the sub-stream, four in flight
-    const uint8_t *data = src + data_start;
-    uint64_t blk = sbeg & ~15ull;
-    auto load = [&](uint64_t off) -> u32x4 {
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (ok && off + 16 <= data_bytes) v = gld128(data + off);
-        return v;
-    };
-    u32x4 q0 = load(blk), q1 = load(blk + 16), q2 = load(blk + 32), q3 = load(blk + 48);
-    blk += 64;
-    uint32_t wi = (uint32_t)(sbeg & 15) >> 2;     // next word of q0
+    // The sub-stream in aligned 16-byte blocks through a buffer resource
+    // bounded to this segment (blocks past its end read as zero). Four
+    // slots are reloaded as soon as their last dword is taken, so every
+    // load has three blocks of decoding to arrive; the slots never move
+    // between registers, so no wait is forced early.
+    const Buf sb = make_buf(seg, ok ? (uint32_t)(b - a) : 0u);
+    uint32_t boff = (uint32_t)(sbeg - a) & ~15u;
+    u32x4 qa = buf_ld128(sb, boff), qb = buf_ld128(sb, boff + 16), qc = buf_ld128(sb, boff + 32),
+          qd = buf_ld128(sb, boff + 48);
+    boff += 64;
+    uint32_t skipw = (uint32_t)(sbeg & 15) >> 2;   // dwords of the first block before the stream
+    uint32_t skipb = 8 * ((uint32_t)sbeg & 3);     // then bytes of the first dword
     uint64_t bb = 0;
-    uint32_t nb = 0;
-    auto refill = [&]() {
-        const uint32_t wd = wi == 0 ? q0.x : wi == 1 ? q0.y : wi == 2 ? q0.z : q0.w;
+    uint32_t nb = 0, i = 0, used = 0, bad = 0;
+    // output: bytes up to the lane's first 16-byte boundary one by one, then
+    // whole 16-byte units from four staging words, then the tail
+    const uint32_t head = min((uint32_t)((16 - ((uintptr_t)out & 15)) & 15), count);
+    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    auto take = [&](uint32_t wd) {
+        if (skipw) { --skipw; return; }
         bb |= (uint64_t)wd << nb;
         nb += 32;
-        if (++wi == 4) {
-            q0 = q1; q1 = q2; q2 = q3; q3 = load(blk);
-            blk += 16;
-            wi = 0;
+        bb >>= skipb;
+        nb -= skipb;
+        skipb = 0;
+        while (nb >= kHufMaxLen && i < count) {
+            const uint32_t e = lut[g][(uint32_t)bb & ((1u << kHufMaxLen) - 1)];
+            const uint32_t l = e >> 8;
+            bad |= l == 0 ? 1u : 0u;
+            bb >>= l;
+            nb -= l;
+            used += l;
+            const uint32_t sym = e & 0xFFu;
+            if (i < head) {
+                gst8(out + i, sym);
+            } else {
+                const uint32_t j = i - head, q = j & 15, v = sym << (8 * (q & 3));
+                w0 |= (q >> 2) == 0 ? v : 0u;
+                w1 |= (q >> 2) == 1 ? v : 0u;
+                w2 |= (q >> 2) == 2 ? v : 0u;
+                w3 |= (q >> 2) == 3 ? v : 0u;
+                if (q == 15) {
+                    u32x4 u;
+                    u.x = w0; u.y = w1; u.z = w2; u.w = w3;
+                    gst128(out + head + j - 15, u);
+                    w0 = w1 = w2 = w3 = 0;
+                }
+            }
+            ++i;
         }
     };
-    refill();
-    refill();
-    {
-        const uint32_t skip = 8 * ((uint32_t)sbeg & 3);
-        bb >>= skip;
-        nb -= skip;
+    while (i < count) {
+        take(qa.x); take(qa.y); take(qa.z); take(qa.w);
+        qa = buf_ld128(sb, boff);
+        take(qb.x); take(qb.y); take(qb.z); take(qb.w);
+        qb = buf_ld128(sb, boff + 16);
+        take(qc.x); take(qc.y); take(qc.z); take(qc.w);
+        qc = buf_ld128(sb, boff + 32);
+        take(qd.x); take(qd.y); take(qd.z); take(qd.w);
+        qd = buf_ld128(sb, boff + 48);
+        boff += 64;
     }
-    uint32_t acc = 0, bad = 0;
-    uint64_t used = 0;
-    const bool out4 = ((uintptr_t)out & 3) == 0;
-    for (uint32_t i = 0; i < count; ++i) {
-        if (nb < 32) refill();
-        const uint32_t e = lut[g][(uint32_t)bb & ((1u << kHufMaxLen) - 1)];
-        const uint32_t l = e >> 8;
-        bad |= l == 0 ? 1u : 0u;
-        bb >>= l;
-        nb -= l;
-        used += l;
-        acc |= (e & 0xFFu) << (8 * (i & 3));
-        if ((i & 3) == 3 || i + 1 == count) {
-            // bytes i - (i & 3) .. i of this lane's range
-            const uint32_t i0 = i & ~3u;
-            if (out4 && i == i0 + 3) {
-                gst32(out + i0, acc);
-            } else {
-                for (uint32_t t = i0; t <= i; ++t) gst8(out + t, acc >> (8 * (t - i0)));
-            }
-            acc = 0;
+    if (count > head) {
+        const uint32_t rem = (count - head) & 15, base = count - rem;
+        for (uint32_t q = 0; q < rem; ++q) {
+            const uint32_t wd = (q >> 2) == 0 ? w0 : (q >> 2) == 1 ? w1 : (q >> 2) == 2 ? w2 : w3;
+            gst8(out + base + q, wd >> (8 * (q & 3)));
         }
     }
-    if (bad || used > 8ull * size) ok = false;
+    if (bad || used > 8u * size) ok = false;
     if (s < nseg && !ok && status) atomicOr(status, 4);
 }
 

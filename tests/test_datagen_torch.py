@@ -39,3 +39,23 @@ def test_torch_recipes_shapes_and_statistics():
     rows, D, dt, sigma = datagen.batch_stream_params(7)
     z = datagen.batch_stream_torch(7, device="cpu")
     assert z.shape == (rows, D) and z.element_size() == dt.itemsize
+
+
+def test_wrap_walk_matches_numpy():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(4)
+    steps = np.rint(rng.laplace(0.0, 3.0, size=(5000, 4))).astype(np.int64)
+    want = ((32768 + np.cumsum(steps, axis=0)) % 65536).astype(np.uint16)
+    got = datagen.wrap_walk_torch(torch.from_numpy(steps)).numpy().view(np.uint16)
+    assert np.array_equal(got, want)
+
+
+def test_laplace_walk_torch_chunks_and_scale():
+    torch = pytest.importorskip("torch")
+    g = torch.Generator()
+    g.manual_seed(1)
+    x = datagen.laplace_walk_uint16_torch(20000, 3, 3.0, g, "cpu", chunk=777).numpy().view(np.uint16)
+    d = (np.diff(x.astype(np.int64), axis=0) + 32768) % 65536 - 32768
+    # continuity across chunks and Laplace(0, 3) steps: mean |step| = 3 (rounded: about 3.0)
+    assert np.abs(d).max() < 200 and abs(np.abs(d).mean() - 3.0) < 0.15
+    assert x[0].astype(np.int64).tolist() != [0, 0, 0]

@@ -145,3 +145,16 @@ def test_entropy_unsupported_cases():
     c = _dev(oracle.compress(datagen.ar2_uint16(1000, 2, seed=1), "fire", 256, entropy=1))
     with pytest.raises(spz.SprintzError):
         spz.BatchDecoder([c])
+
+
+def test_entropy_length_limited_codes():
+    # Laplace-step walks: every segment's byte counts give a Huffman tree
+    # deeper than 11, so every code here comes from the halving rule
+    x = datagen.laplace_walk_uint16(100000, 4, 3.0, seed=3)
+    for f in ("fire", "delta"):
+        ref = oracle.compress(x, f, 2048, entropy=1)
+        got = spz.compress(torch.from_numpy(x.view(np.int16)).cuda(), f, 2048, entropy=1).cpu().numpy().tobytes()
+        # byte 7 holds the dtype code (int16 here, uint16 in the reference)
+        assert got[:7] == ref[:7] and got[8:] == ref[8:]
+        y = spz.decompress(_dev(ref))
+        assert np.array_equal(y.cpu().numpy().view(np.uint16), x)
