@@ -80,7 +80,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--forecaster", default="fire", choices=["fire", "delta"])
-    ap.add_argument("--seg-rows", type=int, default=1024)
+    ap.add_argument("--seg-rows", type=int, default=1024,
+                    help="stream workload: rows per segment; 0 = autotuned among 512, 1024, 2048 (fastest "
+                         "within 1 %% of the ratio of 2^20-row segments, else the smallest container)")
     ap.add_argument("--rotate", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="stream", choices=["stream", "batch", "serve", "dsweep", "huffman"],
@@ -133,10 +135,14 @@ def main():
         return
     dev = torch.device("cuda:0")
     rows, D = 4194304, 8
-    workload = f"ar2_uint16 {rows}x{D} {args.forecaster} seg_rows={args.seg_rows}"
-    print(f"[bench] generating {workload}", file=sys.stderr, flush=True)
+    print(f"[bench] generating ar2_uint16 {rows}x{D}", file=sys.stderr, flush=True)
     x_np = datagen.ar2_uint16(rows, D, seed=1)
     U = x_np.nbytes
+    tune = None
+    if args.seg_rows == 0:
+        args.seg_rows, tune = tune_stream_seg_rows(torch.from_numpy(x_np).to(dev), args.forecaster, spz)
+        print(f"[bench] seg_rows {args.seg_rows} ({tune})", file=sys.stderr, flush=True)
+    workload = f"ar2_uint16 {rows}x{D} {args.forecaster} seg_rows={args.seg_rows}"
 
     base_blob = cpu = None
     if not args.no_cpu_baseline:
@@ -227,7 +233,8 @@ def main():
         "dtype": "u16",
         "data": "synthetic",
         "config": {"workload": workload, "rows": rows, "D": D, "dtype": "uint16", "forecaster": args.forecaster,
-                   "seg_rows": args.seg_rows, "hdr_group": 0, "launch": "plain (one stream per call)"},
+                   "seg_rows": args.seg_rows, "hdr_group": 0, "launch": "plain (one stream per call)",
+                   "seg_rows_tuning": tune},
         "decode_GBps": round(dec_gbps, 2),
         "encode_GBps": round(enc_gbps, 2),
         "decode_ms": round(dec_mean * 1e3, 4),
@@ -255,6 +262,46 @@ def main():
             "u16_fire_decode_GBps", "u16_fire_hbm_frac", "compression_ratio", "parity")}
         out["batched_vs_plain"]["workload"] = b["config"]["workload"]
     print(json.dumps(out), flush=True)
+
+
+def tune_stream_seg_rows(x, forecaster, spz, cands=(512, 1024, 2048), ref_rows=1 << 20):
+    """seg_rows for one stream: the fastest decode among the candidates whose
+    container stays within 1 % of the one with ref_rows-row segments (close
+    to the paper's unsegmented stream); if none does, the smallest container.
+    Returns (seg_rows, {seg_rows: [bytes, best decode us]})."""
+    import torch
+    rows, D = x.shape
+    dt = spz.dtype_code(x)
+    sh = torch.cuda.current_stream().cuda_stream
+    table = {}
+    for S in (ref_rows,) + tuple(cands):
+        enc = spz.Encoder.create(rows, D, dt, spz.make_params(forecaster, S), device=x.device)
+        enc.run(x)
+        torch.cuda.synchronize()
+        csize = int(enc.out_size.item())
+        info = spz.info_of(enc.dst[:64])
+        y = torch.empty_like(x)
+        st = torch.zeros(1, dtype=torch.int32, device=x.device)
+        best = float("inf")
+        for k in range(6):
+            a, b = _events(1)[0]
+            a.record()
+            rc = spz.sprintz_decompress(enc.dst.data_ptr(), csize, info, y.data_ptr(), x.numel() * x.element_size(),
+                                        st.data_ptr(), sh)
+            b.record()
+            if rc != spz.SPZ_OK:
+                raise spz.SprintzError(rc, "sprintz_decompress")
+            torch.cuda.synchronize()
+            if k:
+                best = min(best, a.elapsed_time(b) * 1e3)
+        if not torch.equal(x, y) or int(st.item()) != 0:
+            print(f"[bench] PARITY FAILURE while tuning seg_rows {S}", file=sys.stderr, flush=True)
+            sys.exit(1)
+        table[S] = [csize, round(best, 2)]
+        del enc, y
+    ok = [S for S in cands if table[S][0] <= 1.01 * table[ref_rows][0]]
+    pick = min(ok, key=lambda S: table[S][1]) if ok else min(cands, key=lambda S: table[S][0])
+    return pick, {str(k): v for k, v in table.items()}
 
 
 def _events(n):
