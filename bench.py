@@ -99,8 +99,8 @@ def main():
                     help="only run plain device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the codec has no multi-GPU path in this build "
-              "(segments shard trivially across GPUs; see the design notes). Run with --gpus 1.",
+        print("bench.py measures one GPU only: the codec has no multi-GPU path "
+              "(segments are independent, so decoding shards across GPUs without communication). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -16,9 +16,9 @@
  *   - run-length coding of all-zero blocks (Section 4.1, Algorithm 1/2).
  * Everything is exact integer arithmetic. Bits are handled one at a time.
  *
- * Where the paper leaves a detail open, the reading used here is the one
- * listed in the design notes of this repository (readings R1-R18); each use
- * is marked "reading Rn" below.
+ * Where the paper leaves a detail open, the reading taken is stated where it
+ * is used and marked "reading Rn" (R1-R19), so that the GPU library can take
+ * the same one.
  *
  * Byte format (this implementation's own; the paper's layout figure is not
  * available): little-endian fields, LSB-first bit strings, zero padding.
