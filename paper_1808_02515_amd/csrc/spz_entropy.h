@@ -61,6 +61,7 @@ __global__ __launch_bounds__(256) void k_huff_size(const uint8_t *__restrict__ p
                                                    int32_t *__restrict__ status) {
     __shared__ uint32_t hist[kHufSub][256];
     __shared__ u32x4 f4[64];                     // counts, four per entry
+    __shared__ uint32_t weight[512];
     __shared__ uint32_t order[256];
     __shared__ uint32_t parent[512];
     __shared__ uint32_t len[256];
@@ -121,39 +122,30 @@ __global__ __launch_bounds__(256) void k_huff_size(const uint8_t *__restrict__ p
             __syncthreads();
             break;
         }
-        if (t < 64) {
-            // the merge runs in wavefront 0 with the weights in registers:
-            // node i of a queue sits in lane i % 64 of slot i / 64, read with
-            // readlane and written with a lane select, under uniform control
-            uint32_t lw[4], iw[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-            for (uint32_t q = 0; q < 4; ++q) lw[q] = 64 * q + t < m ? f[order[64 * q + t]] : 0u;
-            auto rd = [](const uint32_t (&A)[4], uint32_t i) -> uint32_t {
-                const uint32_t sl = i >> 6;
-                const uint32_t v = sl == 0 ? A[0] : sl == 1 ? A[1] : sl == 2 ? A[2] : A[3];
-                return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(i & 63));
-            };
-            uint32_t leaf = 0, inner = 0, nint = 0;
+        if (t == 0) {
+            // serial two-queue merge; the next leaf's weight is read one
+            // pick ahead and a fresh internal node is kept in a register
+            for (uint32_t k = 0; k < m; ++k) weight[k] = f[order[k]];
+            uint32_t leaf = 0, inner = m, next = m;
+            uint32_t lw = weight[0];
             for (uint32_t step = 0; step + 1 < m; ++step) {
-                uint32_t node[2], wsum = 0;
-#pragma unroll
+                uint32_t pick[2], wsum = 0;
                 for (int q = 0; q < 2; ++q) {
-                    const bool has_leaf = leaf < m, has_inner = inner < nint;
-                    const uint32_t a_w = has_leaf ? rd(lw, leaf) : 0u;
-                    const uint32_t b_w = has_inner ? rd(iw, inner) : 0u;
-                    const bool use_leaf = has_leaf && (!has_inner || a_w <= b_w);
-                    node[q] = use_leaf ? leaf : m + inner;
-                    wsum += use_leaf ? a_w : b_w;
-                    if (use_leaf) ++leaf; else ++inner;
+                    const uint32_t iw = inner < next ? weight[inner] : 0u;
+                    const bool use_leaf = leaf < m && (inner >= next || lw <= iw);
+                    if (use_leaf) {
+                        pick[q] = leaf++;
+                        wsum += lw;
+                        lw = leaf < m ? weight[leaf] : 0u;
+                    } else {
+                        pick[q] = inner++;
+                        wsum += iw;
+                    }
                 }
-                const uint32_t sl = nint >> 6, ln = nint & 63;
-#pragma unroll
-                for (uint32_t q = 0; q < 4; ++q) iw[q] = (sl == q && t == ln) ? wsum : iw[q];
-                if (t == 0) {
-                    parent[node[0]] = m + nint;
-                    parent[node[1]] = m + nint;
-                }
-                ++nint;
+                weight[next] = wsum;
+                parent[pick[0]] = next;
+                parent[pick[1]] = next;
+                ++next;
             }
         }
         __syncthreads();
