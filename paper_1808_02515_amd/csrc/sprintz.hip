@@ -16,7 +16,6 @@
 
 #include "sprintz.h"
 #include "spz_decode.h"
-#include "spz_decode_chunked.h"
 #include "spz_decode_pc.h"
 #include "spz_encode.h"
 #include "spz_encode_chunked.h"
@@ -120,6 +119,9 @@ hipError_t launch_encode(const void *src, const spz::Geom &g, uint32_t *ws, uint
 // The chunked decoders need one header group per segment and 16-byte
 // aligned output rows; D = 1, 2, 4, 8, 16 take the producer/consumer kernel,
 // other D the phase-split one, and any other container the per-lane walker.
+// The producer/consumer decoder takes whole-segment header groups, D <= 16
+// and 16-byte aligned output rows; everything else (D > 16 too, where it
+// measured faster than a chunked workgroup decoder) takes the walker.
 bool chunked_ok(const spz::Geom &g, uint32_t w, const void *dst) {
     return g.G == 0 && ((uintptr_t)dst & 15) == 0 && ((uint64_t)g.S * g.D * (w / 8)) % 16 == 0;
 }
@@ -142,12 +144,6 @@ hipError_t launch_decode(const void *src, const spz::Geom &g, void *dst, int32_t
             SPZ_PC(9) SPZ_PC(10) SPZ_PC(11) SPZ_PC(12) SPZ_PC(13) SPZ_PC(14) SPZ_PC(15) SPZ_PC(16)
 #undef SPZ_PC
         }
-    } else if (chunked_ok(g, W, dst)) {
-        const uint32_t spw = 64u >> g.dp_log2;
-        const uint32_t grid = (g.nseg + spw - 1) / spw;
-        const uint64_t magic = ((1ull << 32) + g.D - 1) / g.D;  // ceil(2^32 / D)
-        hipLaunchKernelGGL((spz::k_decode_chunked<W, FIRE, COL>), dim3(grid), dim3(spz::kThreads), 0, stream,
-                           (const uint8_t *)src, g, (T *)dst, magic, status);
     } else {
         hipLaunchKernelGGL((spz::k_decode<W, FIRE, COL>), dim3(grid_for(g)), dim3(spz::kThreads), 0, stream,
                            (const uint8_t *)src, g, (T *)dst, status);
