@@ -85,10 +85,12 @@ def main():
                          "within 1 %% of the ratio of 2^20-row segments, else the smallest container)")
     ap.add_argument("--rotate", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="stream", choices=["stream", "batch", "serve", "dsweep", "huffman"],
+    ap.add_argument("--workload", default="stream",
+                    choices=["stream", "batch", "serve", "dsweep", "huffman", "latency"],
                     help="stream: the 4,194,304 x 8 uint16 stream; batch: the many-stream batch; "
                          "serve: the request-serving loop; dsweep: speed against D on uniform values; "
-                         "huffman: the 4 GiB D=4 uint16 walk with and without the entropy stage")
+                         "huffman: the 4 GiB D=4 uint16 walk with and without the entropy stage; "
+                         "latency: the 65,536-sample int8 walk, call latency")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: requests per second (Poisson)")
     ap.add_argument("--streams", type=int, default=10000, help="batch workload: number of streams")
@@ -132,6 +134,9 @@ def main():
         return
     if args.workload == "huffman":
         run_huffman(args)
+        return
+    if args.workload == "latency":
+        run_latency(args)
         return
     dev = torch.device("cuda:0")
     rows, D = 4194304, 8
@@ -503,6 +508,79 @@ def run_batch(args):
         "cpu_baseline": cpu,
     }
     return out
+
+
+def run_latency(args, S=1024):
+    """The small stream: 65,536 x 1 int8 random walk (15 % constant runs),
+    seed 0, both forecasters. Call latency of compress and decompress (HIP
+    events around each call, inputs resident); the container must equal the
+    oracle's in the CPU leg."""
+    import torch
+    import datagen
+    import paper_1808_02515_amd as spz
+
+    x_np = datagen.walk_int8(seed=0)
+    x = torch.from_numpy(x_np).cuda()
+    rows, D = x.shape
+    U = x_np.nbytes
+    sh = torch.cuda.current_stream().cuda_stream
+    res = {}
+    for f in ("delta", "fire"):
+        enc = spz.Encoder.create(rows, D, spz.SPZ_INT8, spz.make_params(f, S))
+        enc.run(x)
+        torch.cuda.synchronize()
+        csize = int(enc.out_size.item())
+        info = spz.info_of(enc.dst[:64])
+        y = torch.empty_like(x)
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        te, td = [], []
+        for k in range(max(args.steps, 1) + 5):
+            a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            a.record()
+            enc.run(x)
+            b.record()
+            rc = spz.sprintz_decompress(enc.dst.data_ptr(), csize, info, y.data_ptr(), U, st.data_ptr(), sh)
+            c.record()
+            if rc != spz.SPZ_OK:
+                raise spz.SprintzError(rc, "sprintz_decompress")
+            torch.cuda.synchronize()
+            if k >= 5:
+                te.append(a.elapsed_time(b) * 1e3)
+                td.append(b.elapsed_time(c) * 1e3)
+        if not torch.equal(x, y) or int(st.item()) != 0 or int(enc.status.item()) != 0:
+            print(f"[bench] PARITY FAILURE latency {f}", file=sys.stderr, flush=True)
+            sys.exit(1)
+        res[f] = {"decode_us_median": round(float(np.median(td)), 2), "decode_us_best": round(min(td), 2),
+                  "encode_us_median": round(float(np.median(te)), 2), "encode_us_best": round(min(te), 2),
+                  "ratio": round(U / csize, 4), "container": enc.dst[:csize].cpu().numpy().tobytes()}
+    cpu = None
+    parity = "decoded samples equal to the input (both forecasters)"
+    if not args.no_cpu_baseline:
+        import oracle
+        secs = []
+        for f in ("delta", "fire"):
+            t1 = time.perf_counter()
+            ref = oracle.compress(x_np, f, S)
+            oracle.decompress(ref)
+            secs.append(time.perf_counter() - t1)
+            if ref != res[f]["container"]:
+                print(f"[bench] PARITY FAILURE (latency container bytes, {f})", file=sys.stderr, flush=True)
+                sys.exit(1)
+        cpu = {"value": round(U / (secs[1] / 2) / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": "the whole 65,536-sample stream, FIRE, encode + decode (rate of one of the two)"}
+        parity += "; container bytes equal to the CPU oracle's"
+    for f in res:
+        del res[f]["container"]
+    out = {
+        "metric": "decode GB/s and encode GB/s (uncompressed bytes), % HBM peak, batched vs plain",
+        "value": round(U / (res["fire"]["decode_us_median"] * 1e-6) / 1e9, 4), "unit": "GB/s", "n_gpus": 1,
+        "steps": max(args.steps, 1), "warmup": 5, "ms_per_step": res["fire"]["decode_us_median"] / 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"walk_int8 {rows}x{D} seg_rows={S}, call latency"},
+        "value_note": "a latency configuration: the call is launch-bound, so the µs figures matter, not %HBM",
+        "delta": res["delta"], "fire": res["fire"], "parity": parity, "roofline": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def run_huffman(args, rows=1 << 29, D=4, S=2048):
