@@ -94,7 +94,7 @@ def main():
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: requests per second (Poisson)")
     ap.add_argument("--streams", type=int, default=10000, help="batch workload: number of streams")
-    ap.add_argument("--batch-streams", type=int, default=1000,
+    ap.add_argument("--batch-streams", type=int, default=10000,
                     help="stream workload: also run this many streams of the batch workload, batched vs one "
                          "launch per stream (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
