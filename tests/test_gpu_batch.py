@@ -146,3 +146,36 @@ def test_batch_graph_replays():
         for i, (x, f, S, G) in enumerate(cases):
             assert np.array_equal(_np(bd.outs[i], x.dtype).reshape(x.shape), x), (rep, i)
     bd.close()
+
+
+def test_batch_large_plan_and_graph_replays():
+    # a plan of over 256 MB in two classes (persistent grids that loop over
+    # many groups): eager runs and replays of a captured graph are exact
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    xs = []
+    for D in (4, 8):
+        steps = torch.randint(-30, 31, (20_000_000 // D * 4, D), generator=g, device="cuda", dtype=torch.int32)
+        xs.append((torch.cumsum(steps, 0) & 0xFFFF).to(torch.int32).to(torch.int16).contiguous())
+    conts = [spz.compress(x, "fire", 2048) for x in xs]
+    assert sum(x.numel() * 2 for x in xs) >= 256 << 20
+    bd = spz.BatchDecoder(conts)
+    bd.run()
+    torch.cuda.synchronize()
+    assert int(bd.status.abs().sum().item()) == 0
+    for x, o in zip(xs, bd.outs):
+        assert torch.equal(o.view(torch.int16), x)
+    s = torch.cuda.Stream()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr, stream=s):
+        bd.run(stream=s)
+    for rep in range(3):
+        for o in bd.outs:
+            o.view(torch.uint8).fill_(rep + 1)
+        torch.cuda.synchronize()
+        gr.replay()
+        torch.cuda.synchronize()
+        assert int(bd.status.abs().sum().item()) == 0
+        for x, o in zip(xs, bd.outs):
+            assert torch.equal(o.view(torch.int16), x), rep
+    bd.close()
