@@ -153,10 +153,10 @@ spz_status sprintz_decompress_ws(const void *d_src, size_t src_size, const spz_i
  * one launch each (the paper's method is unchanged: every segment is decoded
  * exactly as by sprintz_decompress, Algorithm 2 per record).
  *
- * Streams outside the batched kernels (hdr_group != 0, D not in
- * {1, 2, 4, 8, 16}, output not 16-byte aligned, seg_rows * D * w/8 not a
- * multiple of 16) are decoded by the single-container path inside the same
- * call. */
+ * Streams outside the batched kernels (hdr_group != 0, D > 16, output not
+ * 16-byte aligned, seg_rows * D * w/8 not a multiple of 16) are decoded by
+ * the single-container path inside the same call. Entropy-coded containers
+ * are rejected (SPZ_EUNSUPPORTED). */
 typedef struct {
     const void *d_src;   /* container, 16-byte aligned, src_size bytes */
     size_t src_size;

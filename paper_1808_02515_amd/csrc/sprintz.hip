@@ -116,9 +116,6 @@ hipError_t launch_encode(const void *src, const spz::Geom &g, uint32_t *ws, uint
     return hipGetLastError();
 }
 
-// The chunked decoders need one header group per segment and 16-byte
-// aligned output rows; D = 1, 2, 4, 8, 16 take the producer/consumer kernel,
-// other D the phase-split one, and any other container the per-lane walker.
 // The producer/consumer decoder takes whole-segment header groups, D <= 16
 // and 16-byte aligned output rows; everything else (D > 16 too, where it
 // measured faster than a chunked workgroup decoder) takes the walker.
