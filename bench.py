@@ -269,6 +269,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def pick_seg_rows(sizes: dict, times: dict, ref_bytes: int, tol: float = 0.01) -> int:
+    """The autotuner's rule. sizes and times map each candidate seg_rows to
+    its compressed bytes and decode time. Among the candidates whose container
+    is at most (1 + tol) x ref_bytes (the unsegmented container), take the
+    fastest; if none qualifies, take the smallest container. Ties go to the
+    candidate listed first."""
+    ok = [S for S in sizes if sizes[S] <= (1 + tol) * ref_bytes]
+    if ok:
+        return min(ok, key=lambda S: times[S])
+    return min(sizes, key=lambda S: sizes[S])
+
+
 def tune_stream_seg_rows(x, forecaster, spz, cands=(512, 1024, 2048), ref_rows=1 << 20):
     """seg_rows for one stream: the fastest decode among the candidates whose
     container stays within 1 % of the one with ref_rows-row segments (close
@@ -304,8 +316,7 @@ def tune_stream_seg_rows(x, forecaster, spz, cands=(512, 1024, 2048), ref_rows=1
             sys.exit(1)
         table[S] = [csize, round(best, 2)]
         del enc, y
-    ok = [S for S in cands if table[S][0] <= 1.01 * table[ref_rows][0]]
-    pick = min(ok, key=lambda S: table[S][1]) if ok else min(cands, key=lambda S: table[S][0])
+    pick = pick_seg_rows({S: table[S][0] for S in cands}, {S: table[S][1] for S in cands}, table[ref_rows][0])
     return pick, {str(k): v for k, v in table.items()}
 
 
@@ -344,9 +355,9 @@ def autotune_seg_rows(streams, spz, cands=(256, 512, 1024, 2048), per_class=6, i
             bd.close()
             rows_tab.append({"seg_rows": S, "bytes": csz, "loss_vs_unsegmented": round(csz / ref - 1, 4),
                              "decode_ms": round(t, 4)})
-        ok = [r for r in rows_tab if r["bytes"] <= 1.01 * ref]
-        best = min(ok, key=lambda r: r["decode_ms"]) if ok else min(rows_tab, key=lambda r: r["bytes"])
-        out[key] = (best["seg_rows"], rows_tab)
+        pick = pick_seg_rows({r["seg_rows"]: r["bytes"] for r in rows_tab},
+                             {r["seg_rows"]: r["decode_ms"] for r in rows_tab}, ref)
+        out[key] = (pick, rows_tab)
     return out
 
 
