@@ -37,6 +37,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def stream_workload_name(rows: int, D: int, forecaster: str, seg_rows: int) -> str:
+    """Name of the single-stream workload, as the counter summaries key it."""
+    return f"ar2_uint16 {rows}x{D} {forecaster} seg_rows={seg_rows}"
+
+
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
     was taken on the current kernel sources (else None)."""
@@ -147,7 +152,7 @@ def main():
     if args.seg_rows == 0:
         args.seg_rows, tune = tune_stream_seg_rows(torch.from_numpy(x_np).to(dev), args.forecaster, spz)
         print(f"[bench] seg_rows {args.seg_rows} ({tune})", file=sys.stderr, flush=True)
-    workload = f"ar2_uint16 {rows}x{D} {args.forecaster} seg_rows={args.seg_rows}"
+    workload = stream_workload_name(rows, D, args.forecaster, args.seg_rows)
 
     base_blob = cpu = None
     if not args.no_cpu_baseline:
@@ -223,7 +228,7 @@ def main():
     dec_gbps = U / dec_mean / 1e9
     enc_gbps = U / enc_mean / 1e9
     achieved = algo_bytes / dec_mean / 1e9
-    traffic = measured_traffic("k_decode", workload)
+    traffic = measured_traffic("k_decode_pc", workload)
     out = {
         "metric": "decode GB/s and encode GB/s (uncompressed bytes), % HBM peak, batched vs plain",
         "value": round(dec_gbps, 2),
@@ -250,7 +255,7 @@ def main():
         "hbm_frac_decode": round(achieved / HBM_PEAK_GBPS, 4),
         "hbm_frac_encode": round((U + csize) / enc_mean / 1e9 / HBM_PEAK_GBPS, 4),
         "parity": parity,
-        "roofline": {"bound": "hbm", "kernel": "k_decode", "achieved": round(achieved, 2),
+        "roofline": {"bound": "hbm", "kernel": "k_decode_pc", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": algo_bytes},
         "cpu_baseline": cpu,

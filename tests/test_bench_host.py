@@ -45,3 +45,17 @@ def test_more_than_one_gpu_is_refused(n):
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr and r.stdout == ""
+
+
+def test_counter_summary_is_keyed_like_the_bench_lookup():
+    # the default stream workload (4,194,304 x 8 uint16, FIRE, 1024-row
+    # segments) must find its HBM traffic entry under the kernel label the
+    # bench line reports
+    import json
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+        d = json.load(fh)
+    key = "k_decode_pc|" + bench.stream_workload_name(4194304, 8, "fire", 1024)
+    assert key in d
+    e = d[key]
+    assert e["kernel"].startswith("spz::k_decode_pc<")
+    assert e["bytes_per_launch"] > 0 and len(e["source_hash"]) == 16
