@@ -71,7 +71,7 @@ typedef struct {
                               last paragraph); 0 = one group per segment */
     uint32_t learn_shift;  /* FIRE learning rate eta = 2^-learn_shift (paper: eta = 1/2) */
     uint32_t entropy;      /* 0 = none; 1 = Huffman coding of every segment's packed
-                              bytes (Section 4.3, last stage; the coder and its format
+                              bytes (Section 4.4, Entropy Coding; the coder and its format
                               are this library's: one canonical code of at most 11-bit
                               codes per segment, 16 sub-streams). Compression needs
                               a plain container's space in the workspace; the coded
@@ -135,8 +135,8 @@ size_t sprintz_decompress_workspace_size(const spz_info *info);
 
 /* sprintz_decompress with a caller workspace (16-byte aligned, ws_size >=
  * sprintz_decompress_workspace_size; ignored for plain containers). Each
- * segment is Huffman-decoded into the workspace (the inverse of Section 4.3's
- * last stage), then decoded as by sprintz_decompress. A corrupt coded segment
+ * segment is Huffman-decoded into the workspace (the inverse of Section 4.4,
+ * Entropy Coding), then decoded as by sprintz_decompress. A corrupt coded segment
  * sets bit 2 of *d_status. sprintz_decompress on an entropy-coded container
  * does the same with a stream-ordered allocation (hipMallocAsync /
  * hipFreeAsync) of the workspace. Batched plans reject entropy-coded

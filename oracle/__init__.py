@@ -136,7 +136,7 @@ def compress(x: np.ndarray, forecaster: str = "fire", seg_rows: int | None = Non
 
 
 def entropy_encode(plain: bytes) -> bytes:
-    """Plain container -> Huffman-coded container (Section 4.3's entropy stage)."""
+    """Plain container -> Huffman-coded container (Section 4.4's entropy stage)."""
     src = np.frombuffer(plain, dtype=np.uint8)
     cap = int(_load().oracle_entropy_bound(src.ctypes.data, len(plain)))
     if cap == 0:

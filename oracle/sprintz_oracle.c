@@ -686,7 +686,7 @@ static int decompress_plain(const uint8_t *src, size_t n, void *dst, size_t cap)
 /* Entropy stage: Huffman coding of each segment's packed bytes              */
 /* ------------------------------------------------------------------------ */
 /*
- * Section 4.3 ends with an entropy stage: the bit-packed bytes are Huffman
+ * Section 4.4 ends with an entropy stage: the bit-packed bytes are Huffman
  * coded with an off-the-shelf byte-oriented coder, bytes taken as symbols
  * regardless of the data's bit width. The coder and its format are not part
  * of the paper; this implementation uses its own (reading R19):

@@ -221,7 +221,7 @@ size_t sprintz_workspace_size(uint64_t rows, uint32_t D, spz_dtype dtype, const 
 }
 
 // Entropy-coded compression: the plain container into the workspace, then
-// the Huffman size pass, offsets and write pass (Section 4.3's last stage).
+// the Huffman size pass, offsets and write pass (Section 4.4).
 static spz_status compress_entropy(const void *d_src, uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p,
                             void *d_dst, size_t dst_cap, uint64_t *d_out_size, void *d_ws, int32_t *d_status,
                             hipStream_t stream) {
@@ -311,7 +311,13 @@ spz_status sprintz_get_info(const void *h_src, size_t n, spz_info *out) {
     if (info.params.forecaster > 1 || info.params.learn_shift > 8 || info.params.entropy > 1) return SPZ_ECORRUPT;
     if (info.params.seg_rows < 8 || info.params.seg_rows % 8 != 0) return SPZ_ECORRUPT;
     if (num_segments(info.rows, info.params.seg_rows) != info.nseg) return SPZ_ECORRUPT;
-    info.compressed_size = align16(kHeader + 8ull * (info.nseg + 1)) + data_bytes;
+    // every size must be representable: a data_bytes or a row count near 2^64
+    // would otherwise wrap the container or output size and pass the checks
+    // of check_decompress with an out-of-range extent
+    const uint64_t data_start = align16(kHeader + 8ull * (info.nseg + 1));
+    if (data_bytes > UINT64_MAX - data_start || data_bytes % 16 != 0) return SPZ_ECORRUPT;
+    if (info.rows > UINT64_MAX / ((uint64_t)info.D * (info.w / 8))) return SPZ_ECORRUPT;
+    info.compressed_size = data_start + data_bytes;
     info.decompressed_size = info.rows * info.D * (info.w / 8);
     *out = info;
     return SPZ_OK;
@@ -331,6 +337,11 @@ spz_status check_decompress(const void *d_src, size_t src_size, const spz_info *
     if (info->D == 0) return SPZ_EINVAL;
     if (info->D > kMaxD) return SPZ_EUNSUPPORTED;
     if (info->nseg != num_segments(info->rows, info->params.seg_rows)) return SPZ_EINVAL;
+    // the container's data must start inside it and the output size must not
+    // wrap (a hand-made info could hold either)
+    const uint64_t data_start = align16(kHeader + 8ull * ((uint64_t)info->nseg + 1));
+    if (info->compressed_size < data_start) return SPZ_EINVAL;
+    if (info->rows > UINT64_MAX / ((uint64_t)info->D * (w / 8))) return SPZ_EINVAL;
     if (info->compressed_size > src_size) return SPZ_ENOSPC;
     if (dst_cap < info->rows * info->D * (w / 8)) return SPZ_ENOSPC;
     if (info->rows > 0 && !d_dst) return SPZ_EINVAL;

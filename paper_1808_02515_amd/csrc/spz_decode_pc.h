@@ -33,8 +33,18 @@
 // A block inside a run of zero blocks decodes as a block whose errors are
 // all 0 (reading R9: the prediction alone; sgn(0) = 0 leaves the FIRE
 // accumulator as it is), so runs need no separate path. One barrier per chunk
-// hands the error buffers over (double buffered). Every global access goes
-// through a bounded buffer resource; every LDS access is aligned.
+// hands the error buffers over (double buffered). Every LDS access is aligned.
+//
+// Global accesses are plain loads and stores, each behind an explicit range
+// check:
+//   - offset-table reads: entries seg and seg + 1 with seg < nseg, inside the
+//     table, which ends before the data start;
+//   - segment reads (record count, staged 16-byte windows, raw tail): only
+//     when the segment's offsets a <= b <= data_bytes are 16-aligned, and
+//     only whole units with off + 16 <= b - a (tail: cursor + tail bytes <=
+//     b - a). The host bounds data_start + data_bytes by the container size;
+//   - output stores: rows of the segment's own whole blocks (tail: its own
+//     tail rows), so below rows * D * w/8 <= the destination capacity.
 #pragma once
 
 #include "spz_device.h"
@@ -433,7 +443,8 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
                     if (WB == 2) E = (i & 1) ? (int32_t)(ev[i >> 1] & 0xFFFF0000u) : (int32_t)(ev[i >> 1] << 16);
                     else E = __builtin_amdgcn_sbfe((int32_t)ev[i >> 2], 8 * (i & 3), 8) << 8;
                     if (FIRE) {
-                        const int32_t tt = E + __mul24(alpha, delta);
+                        // wrapping sum: only bits [w, 2w) are used
+                        const int32_t tt = (int32_t)((uint32_t)E + (uint32_t)__mul24(alpha, delta));
                         if (i & 1) grad += __mul24(sgn_med3(E), delta);
                         delta = __builtin_amdgcn_sbfe(tt, (uint32_t)W, (uint32_t)W);
                         x += (uint32_t)delta;

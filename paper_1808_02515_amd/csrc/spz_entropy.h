@@ -1,7 +1,7 @@
 // Entropy stage of the gfx950 Sprintz codec: Huffman coding of every
 // segment's packed bytes.
 //
-// Paper: Section 4.3 closes the pipeline with a byte-oriented Huffman coder
+// Paper: Section 4.4 closes the pipeline with a byte-oriented Huffman coder
 // run over the bit-packed headers and payloads (bytes are the symbols,
 // whatever the data's bit width). The coder and its byte format are this
 // library's own (the paper uses an external coder):
@@ -443,6 +443,7 @@ __global__ __launch_bounds__(64) void k_huff_decode(const uint8_t *__restrict__ 
     uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
     auto take = [&](uint32_t wd) {
         if (skipw) { --skipw; return; }
+        if (i >= count) return;   // past the last symbol: nb would grow past 64
         bb |= (uint64_t)wd << nb;
         nb += 32;
         bb >>= skipb;

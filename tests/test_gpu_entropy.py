@@ -1,4 +1,4 @@
-"""GPU parity of the entropy stage (Section 4.3's Huffman coding of the
+"""GPU parity of the entropy stage (Section 4.4's Huffman coding of the
 packed bytes; coder and format per reading R19).
 
 Containers coded on the GPU must equal the oracle's byte for byte, and GPU

@@ -1,4 +1,4 @@
-"""Pins of the oracle's entropy stage (Section 4.3: Huffman coding of the
+"""Pins of the oracle's entropy stage (Section 4.4: Huffman coding of the
 bit-packed bytes; the coder and its format follow reading R19).
 
 The lengths are pinned to what holds for any Huffman code, computed here

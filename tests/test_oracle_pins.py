@@ -178,7 +178,7 @@ def test_fire_learns_positive_ramp_hand_derived():
     # (row 1 sees delta 0) give acc = 15; each later block adds 4 x 5 = 20
     # while alpha < 256, so acc_b = 20 b - 5 and alpha_b = floor(acc_b / 8).
     # At b = 103 the accumulator saturates at 2^8 x 8, alpha = 256 (double
-    # delta) and every error is 0 from then on ("constant slopes", Sec. 5.6).
+    # delta) and every error is 0 from then on ("constant slopes", Section 5.7).
     nb = 140
     x = _ramp(5, 8 * nb)
     e, a = oracle.residuals(x, "fire")
