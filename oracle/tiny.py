@@ -149,3 +149,120 @@ def compress(x: np.ndarray, forecaster: str = "fire", seg_rows: int | None = Non
     pre = head + table
     pre += b"\0" * (-len(pre) % 16)
     return pre + b"".join(segs)
+
+
+# ---------------------------------------------------------------------------
+# Entropy stage (Section 4.4, Entropy Coding): Huffman coding of the packed
+# bytes of each segment, in this library's own format (reading R19). Written
+# from the reading, not from the C oracle: the tree is built by merging lists
+# of the leaves below each node, and every merge adds one bit to each of them.
+# ---------------------------------------------------------------------------
+HUF_MAXLEN = 11
+HUF_NSUB = 16
+
+
+def _halve_up(c: int) -> int:
+    return (c + 1) // 2
+
+
+def huff_lengths(counts, halve=_halve_up, max_rounds=None, limit=HUF_MAXLEN) -> list:
+    """Code length of each byte value 0..255 (0 = absent). Two-queue Huffman
+    construction over the present values sorted by (count, value): the next
+    node is the front leaf unless the front internal node weighs strictly
+    less. While a length exceeds 11 bits, every count goes through `halve`
+    and the construction starts again (`max_rounds` caps the number of
+    halvings, `limit` is the longest allowed length; these parameters exist so
+    that tests can plant other rules)."""
+    present = [v for v in range(256) if counts[v] > 0]
+    lengths = [0] * 256
+    if len(present) == 1:
+        lengths[present[0]] = 1
+    if len(present) <= 1:
+        return lengths
+    weight = {v: int(counts[v]) for v in present}
+    rounds = 0
+    while True:
+        leaves = [(weight[v], [v]) for v in sorted(present, key=lambda v: (weight[v], v))]
+        inner = []
+        depth = dict.fromkeys(present, 0)
+        li = ii = 0
+        for _ in range(len(present) - 1):
+            picked = []
+            for _t in range(2):
+                if li < len(leaves) and (ii >= len(inner) or leaves[li][0] <= inner[ii][0]):
+                    picked.append(leaves[li])
+                    li += 1
+                else:
+                    picked.append(inner[ii])
+                    ii += 1
+            below = picked[0][1] + picked[1][1]
+            for v in below:
+                depth[v] += 1
+            inner.append((picked[0][0] + picked[1][0], below))
+        if max(depth.values()) <= limit or (max_rounds is not None and rounds >= max_rounds):
+            for v in present:
+                lengths[v] = depth[v]
+            return lengths
+        weight = {v: halve(weight[v]) for v in present}
+        rounds += 1
+
+
+def huff_canonical(lengths) -> dict:
+    """value -> (code, length): values in (length, value) order get
+    consecutive codes, shifted left once per extra bit of length."""
+    lengths = [int(l) for l in lengths]
+    codes, code, prev = {}, 0, None
+    for v in sorted((v for v in range(256) if lengths[v]), key=lambda v: (lengths[v], v)):
+        if prev is not None:
+            code = (code + 1) << (lengths[v] - prev)
+        codes[v] = (code, lengths[v])
+        prev = lengths[v]
+    return codes
+
+
+def huff_encode_segment(plain: bytes, **rule) -> bytes:
+    """u32 n | 128 bytes of 4-bit lengths (even values low) | 16 x u32
+    sub-stream sizes | 16 sub-streams | zero pad to 16 bytes."""
+    n = len(plain)
+    assert n % HUF_NSUB == 0
+    counts = [0] * 256
+    for b in plain:
+        counts[b] += 1
+    lengths = huff_lengths(counts, **rule)
+    codes = huff_canonical(lengths)
+    m = n // HUF_NSUB
+    subs = []
+    for k in range(HUF_NSUB):
+        bits = _Bits()
+        for b in plain[k * m:(k + 1) * m]:
+            code, l = codes[b]
+            for t in reversed(range(l)):      # most significant bit first
+                bits.put((code >> t) & 1, 1)
+        bits.pad_to_byte()
+        subs.append(bits.to_bytes())
+    out = bytearray(struct.pack("<I", n))
+    out += bytes(lengths[v] | (lengths[v + 1] << 4) for v in range(0, 256, 2))
+    out += b"".join(struct.pack("<I", len(s)) for s in subs)
+    out += b"".join(subs)
+    out += b"\0" * (-len(out) % 16)
+    return bytes(out)
+
+
+def entropy_encode(plain_container: bytes) -> bytes:
+    """A plain container with every segment replaced by its Huffman-coded
+    form; header byte 11 = 1, offsets and data size describe the coded
+    segments."""
+    nseg = struct.unpack_from("<I", plain_container, 28)[0]
+    data_start = -(-(64 + 8 * (nseg + 1)) // 16) * 16
+    offs = struct.unpack_from(f"<{nseg + 1}Q", plain_container, 64)
+    coded = [huff_encode_segment(plain_container[data_start + offs[s]:data_start + offs[s + 1]])
+             for s in range(nseg)]
+    new = [0]
+    for c in coded:
+        new.append(new[-1] + len(c))
+    head = bytearray(plain_container[:64])
+    head[11] = 1
+    head[32:40] = struct.pack("<Q", new[-1])
+    pre = bytes(head) + b"".join(struct.pack("<Q", o) for o in new)
+    pre += b"\0" * (data_start - len(pre))
+    return pre + b"".join(coded)

@@ -14,6 +14,7 @@ import pytest
 
 import datagen
 import oracle
+import oracle.tiny as tiny
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "huffman_hand.txt")
 
@@ -150,3 +151,132 @@ def test_full_alphabet_optimal():
     cost, depth = _heap_huffman(counts)
     assert depth <= 11
     assert int((counts * lens).sum()) == cost and _kraft(lens) == 1.0
+
+
+LIMIT_GOLD = os.path.join(os.path.dirname(__file__), "golden", "huffman_limit_hand.txt")
+
+
+def _limit_golden():
+    kv = {}
+    for line in open(LIMIT_GOLD):
+        if line.strip() and not line.startswith("#"):
+            parts = line.split()
+            kv[parts[0]] = parts[1:]
+
+    def table(key, conv):
+        return {ord(it.split("=")[0]): conv(it.split("=")[1]) for it in kv[key]}
+
+    return (table("counts", int), table("halved", int), table("lengths", int), table("codes", str),
+            bytes.fromhex(kv["len_table_48_54"][0]))
+
+
+def _decode_with(codes, stream: bytes, count: int) -> bytes:
+    """Prefix-decode `count` symbols of a byte-aligned LSB-first bit stream in
+    which each code is stored from its first (most significant) bit on."""
+    inv = {c: v for v, c in codes.items()}
+    bits = "".join(format(b, "08b")[::-1] for b in stream)
+    out, cur = bytearray(), ""
+    for ch in bits:
+        cur += ch
+        if cur in inv:
+            out.append(inv[cur])
+            cur = ""
+            if len(out) == count:
+                break
+    assert len(out) == count
+    return bytes(out)
+
+
+def test_length_limited_code_hand_worked():
+    counts_d, halved_d, lengths_d, codes_d, len_table = _limit_golden()
+    counts = np.zeros(256, np.uint64)
+    for v, c in counts_d.items():
+        counts[v] = c
+    assert sum(counts_d.values()) % 16 == 0
+    # the golden's own halving arithmetic, and that the unlimited tree is too deep
+    assert {v: (c + 1) // 2 for v, c in counts_d.items()} == halved_d
+    assert max(tiny.huff_lengths(list(counts), max_rounds=0)) == 12
+    want = np.zeros(256, np.uint8)
+    for v, l in lengths_d.items():
+        want[v] = l
+    assert list(oracle.huff_lengths(counts)) == list(want)          # the C oracle
+    assert tiny.huff_lengths(list(counts)) == list(want)            # the Python twin
+    assert tiny.huff_canonical(list(want)) == {v: (int(s, 2), len(s)) for v, s in codes_d.items()}
+    # a coded segment of these bytes in a seeded order: its length table and
+    # every sub-stream decode with the hand-worked codes
+    rng = np.random.default_rng(21)
+    plain = bytes(rng.permutation(np.repeat(np.array(list(counts_d)), list(counts_d.values()))).astype(np.uint8))
+    seg = oracle.huff_encode_segment(plain)
+    assert seg == tiny.huff_encode_segment(plain)
+    assert int.from_bytes(seg[:4], "little") == len(plain)
+    table = seg[4:132]
+    assert table[48:55] == len_table and not any(table[:48]) and not any(table[55:])
+    m = len(plain) // 16
+    sizes = [int.from_bytes(seg[132 + 4 * k:136 + 4 * k], "little") for k in range(16)]
+    pos = 196
+    for k in range(16):
+        sub = plain[k * m:(k + 1) * m]
+        assert sizes[k] == -(-sum(lengths_d[b] for b in sub) // 8)
+        assert _decode_with(codes_d, seg[pos:pos + sizes[k]], m) == sub
+        pos += sizes[k]
+
+
+def test_length_limit_golden_rejects_other_rules():
+    # the hand-worked case tells the reading's rule apart from near misses,
+    # each planted in the Python twin
+    counts_d, _, lengths_d, _, _ = _limit_golden()
+    counts = [0] * 256
+    for v, c in counts_d.items():
+        counts[v] = c
+    want = [0] * 256
+    for v, l in lengths_d.items():
+        want[v] = l
+    assert tiny.huff_lengths(counts) == want
+    assert tiny.huff_lengths(counts, halve=lambda c: c // 2 + 1) != want        # other rounding of the halving
+    assert tiny.huff_lengths(counts, halve=lambda c: max(1, c // 2)) != want    # floor, kept present
+    assert tiny.huff_lengths(counts, max_rounds=0) != want                      # one halving fewer
+    assert tiny.huff_lengths(counts, limit=10) != want                          # limit off by one
+    assert tiny.huff_lengths(counts, limit=12) != want
+
+
+def _plain_segments(rng):
+    """Plain segments of oracle containers: Laplace walks (the 4 GiB D = 4
+    uint16 workload's recipe, at small sizes), AR(2), int8 walks, uniform
+    bytes, plus raw byte strings of skewed distributions."""
+    segs = []
+    for k in range(6):
+        x = datagen.laplace_walk_uint16(2048 * 4 + 16 * k, 4, scale=3.0, seed=30 + k)
+        c = oracle.compress(x, "fire", 2048)
+        nseg = int.from_bytes(c[28:32], "little")
+        ds = (64 + 8 * (nseg + 1) + 15) & ~15
+        offs = [int.from_bytes(c[64 + 8 * s:72 + 8 * s], "little") for s in range(nseg + 1)]
+        segs += [c[ds + offs[s]:ds + offs[s + 1]] for s in range(nseg)]
+    for x, S in [(datagen.ar2_uint16(4096, 8, seed=40), 512), (datagen.walk_int8(8192, 1, seed=41), 1024),
+                 (datagen.uniform(2048, 2, np.uint8, seed=42), 256)]:
+        c = oracle.compress(x, "delta", S)
+        nseg = int.from_bytes(c[28:32], "little")
+        ds = (64 + 8 * (nseg + 1) + 15) & ~15
+        offs = [int.from_bytes(c[64 + 8 * s:72 + 8 * s], "little") for s in range(nseg + 1)]
+        segs += [c[ds + offs[s]:ds + offs[s + 1]] for s in range(nseg)]
+    for k in range(60):
+        n = 16 * int(rng.integers(1, 200))
+        p = np.minimum(rng.geometric(float(rng.uniform(0.05, 0.9)), size=n) - 1, 255).astype(np.uint8)
+        segs.append(p.tobytes())
+    return segs
+
+
+def test_c_oracle_equals_python_twin_on_many_segments():
+    rng = np.random.default_rng(3)
+    segs = _plain_segments(rng)
+    assert len(segs) >= 100
+    limited = 0
+    for s in segs:
+        counts = np.bincount(np.frombuffer(s, np.uint8), minlength=256)
+        if max(tiny.huff_lengths(list(counts), max_rounds=0)) > 11:
+            limited += 1
+        assert oracle.huff_encode_segment(s) == tiny.huff_encode_segment(s)
+    assert limited >= 20, limited   # the length limit is exercised, not only the plain construction
+    # whole containers, header and offsets included
+    x = datagen.laplace_walk_uint16(2048 * 3 + 5, 4, scale=3.0, seed=50)
+    plain = oracle.compress(x, "fire", 2048)
+    assert oracle.entropy_encode(plain) == tiny.entropy_encode(plain)
