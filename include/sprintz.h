@@ -115,6 +115,22 @@ spz_status sprintz_compress(const void *d_src, uint64_t rows, uint32_t D, spz_dt
                             const spz_params *p, void *d_dst, size_t dst_cap, uint64_t *d_out_size,
                             void *d_ws, size_t ws_size, int32_t *d_status, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * sprintz_compress without a workspace argument. The workspace is a static
+ * device array of 4 MiB (4,194,304 bytes) inside the library, one per GPU, held until the process ends; its address
+ * is looked up once per device on the first call there. The call allocates
+ * nothing and otherwise behaves exactly as sprintz_compress (same kernels,
+ * same bytes, same argument checks). Requests whose sprintz_workspace_size
+ * exceeds the array (more than 524,287 segments, or entropy = 1 beyond a
+ * small shape) return SPZ_ENOSPC before anything is enqueued. All calls on
+ * one GPU share its array: calls that overlap in time on that GPU (on
+ * different streams, or from different threads) race and must not be
+ * issued; calls ordered on one stream are fine. */
+spz_status sprintz_compress_noalloc(const void *d_src, uint64_t rows, uint32_t D, spz_dtype dtype,
+                                    const spz_params *p, void *d_dst, size_t dst_cap, uint64_t *d_out_size,
+                                    int32_t *d_status, hipStream_t stream);
+
 /* Parse the 64-byte container header from a host copy of at least 64
  * bytes. SPZ_ECORRUPT if it is not a valid header. */
 spz_status sprintz_get_info(const void *h_src, size_t n, spz_info *out);

@@ -58,6 +58,9 @@ _SIGNATURES = {
                                         ctypes.POINTER(spz_params), ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                         ctypes.c_void_p]),
+    "sprintz_compress_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
+                                                ctypes.POINTER(spz_params), ctypes.c_void_p, ctypes.c_size_t,
+                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sprintz_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(spz_info)]),
     "sprintz_decompress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(spz_info),
                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
@@ -127,6 +130,16 @@ def sprintz_compress(d_src: int, rows: int, D: int, dtype: int, p: spz_params, d
                      d_out_size: int, d_ws: int, ws_size: int, d_status: int, stream: int) -> int:
     return int(load().sprintz_compress(d_src, rows, D, dtype, ctypes.byref(p), d_dst, dst_cap, d_out_size, d_ws,
                                        ws_size, d_status, stream))
+
+
+#: bytes of the static device workspace of sprintz_compress_noalloc
+NOALLOC_WORKSPACE_BYTES = 4 << 20
+
+
+def sprintz_compress_noalloc(d_src: int, rows: int, D: int, dtype: int, p: spz_params, d_dst: int, dst_cap: int,
+                             d_out_size: int, d_status: int, stream: int) -> int:
+    return int(load().sprintz_compress_noalloc(d_src, rows, D, dtype, ctypes.byref(p), d_dst, dst_cap, d_out_size,
+                                               d_status, stream))
 
 
 def sprintz_get_info(h_src: bytes) -> spz_info:

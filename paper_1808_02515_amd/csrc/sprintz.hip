@@ -154,6 +154,29 @@ uint64_t get_le(const uint8_t *p, int n) {
     return v;
 }
 
+// Compression workspace of sprintz_compress_noalloc: a device array of fixed
+// size that every GPU the library runs on holds until the process ends. In
+// host code its name is only a stand-in; kernels get the device address that
+// hipGetSymbolAddress returns, looked up once per device.
+constexpr size_t kScratchBytes = 4u << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;   // device -> address of its scratch array
+
+spz_status scratch_address(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SPZ_EHIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) { *out = it->second; return SPZ_OK; }
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return SPZ_EHIP;
+    g_scratch_ptr[dev] = p;
+    *out = p;
+    return SPZ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -287,6 +310,21 @@ spz_status sprintz_compress(const void *d_src, uint64_t rows, uint32_t D, spz_dt
     }
 #undef SPZ_ENC
     return e == hipSuccess ? SPZ_OK : SPZ_EHIP;
+}
+
+spz_status sprintz_compress_noalloc(const void *d_src, uint64_t rows, uint32_t D, spz_dtype dtype,
+                                    const spz_params *p, void *d_dst, size_t dst_cap, uint64_t *d_out_size,
+                                    int32_t *d_status, hipStream_t stream) {
+    // the same kernels as sprintz_compress, with the library's scratch array
+    // as the workspace; every value the kernels read from it is written by
+    // the same call first, so nothing needs clearing between calls
+    const size_t need = sprintz_workspace_size(rows, D, dtype, p);
+    if (need > kScratchBytes) return SPZ_ENOSPC;
+    void *ws = nullptr;
+    const spz_status st = scratch_address(&ws);
+    if (st != SPZ_OK) return st;
+    return sprintz_compress(d_src, rows, D, dtype, p, d_dst, dst_cap, d_out_size, ws, kScratchBytes, d_status,
+                            stream);
 }
 
 spz_status sprintz_get_info(const void *h_src, size_t n, spz_info *out) {
