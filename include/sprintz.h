@@ -99,16 +99,28 @@ void spz_params_default(spz_params *p);
  * arguments are invalid. */
 size_t sprintz_compress_bound(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p);
 
-/* Bytes of device workspace sprintz_compress needs (8 per segment; with
- * entropy = 1 also the plain container, its workspace and 256 bytes per
- * segment for the code records). */
+/* Bytes of device workspace for the fastest compression of this shape. With
+ * hdr_group 0 and D <= 16 that is the single-pass encoder's: every segment
+ * is coded once into a slot of the workspace (its largest size) and then
+ * copied to its place, plus 16 bytes per segment. Otherwise 8 bytes per
+ * segment (two passes over the input). With entropy = 1 also the plain
+ * container, its workspace and 256 bytes per segment for the code records. */
 size_t sprintz_workspace_size(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p);
+
+/* Smallest workspace sprintz_compress accepts: 8 bytes per segment + 8 (the
+ * two-pass encoder, which reads the input twice; the same bytes). Equal to
+ * sprintz_workspace_size when entropy = 1. 0 if the arguments are invalid. */
+size_t sprintz_workspace_size_min(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p);
 
 /* Compress d_src, a row-major (rows, D) array of `dtype` (alignment: the
  * element size), into the container d_dst (16-byte aligned, dst_cap >=
  * sprintz_compress_bound). The container's byte count is written to the
  * device word *d_out_size (required). d_ws (8-byte aligned, ws_size >=
- * sprintz_workspace_size) holds per-segment sizes between the kernels.
+ * sprintz_workspace_size_min) holds the segments' sizes (and with the
+ * single-pass encoder their coded bytes) between the kernels; the
+ * single-pass encoder runs when ws_size >= sprintz_workspace_size, d_ws and
+ * d_src are 16-byte aligned and seg_rows * D * w/8 is a multiple of 16. The
+ * container is the same either way.
  * Algorithm 1 (encodeBlock) per block, forecasters of Section 4.2, bit
  * packing of Section 4.3. */
 spz_status sprintz_compress(const void *d_src, uint64_t rows, uint32_t D, spz_dtype dtype,
@@ -121,9 +133,11 @@ spz_status sprintz_compress(const void *d_src, uint64_t rows, uint32_t D, spz_dt
  * device array of 4 MiB (4,194,304 bytes) inside the library, one per GPU, held until the process ends; its address
  * is looked up once per device on the first call there. The call allocates
  * nothing and otherwise behaves exactly as sprintz_compress (same kernels,
- * same bytes, same argument checks). Requests whose sprintz_workspace_size
- * exceeds the array (more than 524,287 segments, or entropy = 1 beyond a
- * small shape) return SPZ_ENOSPC before anything is enqueued. All calls on
+ * same bytes, same argument checks); the single-pass encoder when its
+ * workspace fits the array, else the two-pass one. Requests whose
+ * sprintz_workspace_size_min exceeds the array (more than 524,287 segments,
+ * or entropy = 1 beyond a small shape) return SPZ_ENOSPC before anything is
+ * enqueued. All calls on
  * one GPU share its array: calls that overlap in time on that GPU (on
  * different streams, or from different threads) race and must not be
  * issued; calls ordered on one stream are fine. */

@@ -54,6 +54,8 @@ _SIGNATURES = {
                                                  ctypes.POINTER(spz_params)]),
     "sprintz_workspace_size": (ctypes.c_size_t, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
                                                  ctypes.POINTER(spz_params)]),
+    "sprintz_workspace_size_min": (ctypes.c_size_t, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
+                                                     ctypes.POINTER(spz_params)]),
     "sprintz_compress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
                                         ctypes.POINTER(spz_params), ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
@@ -124,6 +126,10 @@ def sprintz_compress_bound(rows: int, D: int, dtype: int, p: spz_params) -> int:
 
 def sprintz_workspace_size(rows: int, D: int, dtype: int, p: spz_params) -> int:
     return int(load().sprintz_workspace_size(rows, D, dtype, ctypes.byref(p)))
+
+
+def sprintz_workspace_size_min(rows: int, D: int, dtype: int, p: spz_params) -> int:
+    return int(load().sprintz_workspace_size_min(rows, D, dtype, ctypes.byref(p)))
 
 
 def sprintz_compress(d_src: int, rows: int, D: int, dtype: int, p: spz_params, d_dst: int, dst_cap: int,

@@ -19,6 +19,7 @@
 #include "spz_decode_pc.h"
 #include "spz_encode.h"
 #include "spz_encode_chunked.h"
+#include "spz_encode_sp.h"
 #include "spz_entropy.h"
 
 namespace {
@@ -86,6 +87,57 @@ bool enc_chunked_ok(const spz::Geom &g, uint32_t w, const void *src) {
     const uint64_t hdr_seg = (spz::enc_hdr_cap(g.S >> 3, g.D, w) + 15) & ~15ull;
     const uint64_t out_seg = ((uint64_t)cb * 8 * g.D * (w / 8) + 6 * cb + 15) & ~15ull;
     return spw * hdr_seg <= (uint64_t)spz::kEncHdrBytes && spw * out_seg <= 4ull * spz::kEncOutWords;
+}
+
+// The single-pass encoder takes whole-segment header groups, D <= 16,
+// 16-byte aligned input rows of every segment and a 16-byte aligned
+// workspace of sp_workspace_bytes; the two-pass encoders below need only
+// 8 bytes per segment.
+bool enc_sp_ok(const spz::Geom &g, uint32_t w, const void *src, const void *ws) {
+    return g.G == 0 && g.D >= 1 && g.D <= 16 && !((uintptr_t)src & 15) && !((uintptr_t)ws & 15) &&
+           ((uint64_t)g.S * g.D * (w / 8)) % 16 == 0;
+}
+
+uint64_t sp_slot_stride(uint32_t S, uint32_t D, uint32_t w) { return spz::es_slot_bytes(S >> 3, D, w); }
+
+size_t sp_workspace_bytes(uint64_t nseg, uint32_t S, uint32_t D, uint32_t w) {
+    return align256(16 * (size_t)nseg) + (size_t)(nseg * sp_slot_stride(S, D, w));
+}
+
+template <int W, bool FIRE, int D>
+void launch_enc_sp_kernel(const void *src, const spz::Geom &g, uint8_t *slots, uint64_t stride, spz::u32x4 *info,
+                          hipStream_t stream) {
+    using G = spz::EsGeom<W, D>;
+    const uint32_t grid = (g.nseg + G::SPW - 1) / G::SPW;
+    hipLaunchKernelGGL((spz::k_encode_sp<W, FIRE, D>), dim3(grid), dim3(G::NT), 0, stream, (const uint8_t *)src, g,
+                       slots, stride, info);
+}
+
+template <int W, bool FIRE>
+hipError_t launch_encode_sp(const void *src, const spz::Geom &g, uint8_t *ws, uint8_t *dst, int32_t *status,
+                            uint32_t dtype, uint32_t forecaster, uint32_t learn_shift, uint64_t *out_size,
+                            hipStream_t stream) {
+    const uint64_t stride = sp_slot_stride(g.S, g.D, W);
+    spz::u32x4 *info = reinterpret_cast<spz::u32x4 *>(ws);
+    uint8_t *slots = ws + align256(16 * (size_t)g.nseg);
+    if (g.nseg > 0) {
+        switch (g.D) {
+#define SPZ_ESP(D_) case D_: launch_enc_sp_kernel<W, FIRE, D_>(src, g, slots, stride, info, stream); break;
+            SPZ_ESP(1) SPZ_ESP(2) SPZ_ESP(3) SPZ_ESP(4) SPZ_ESP(5) SPZ_ESP(6) SPZ_ESP(7) SPZ_ESP(8)
+            SPZ_ESP(9) SPZ_ESP(10) SPZ_ESP(11) SPZ_ESP(12) SPZ_ESP(13) SPZ_ESP(14) SPZ_ESP(15) SPZ_ESP(16)
+#undef SPZ_ESP
+            default: return hipErrorInvalidValue;
+        }
+    }
+    hipLaunchKernelGGL(spz::k_enc_scan, dim3(1), dim3(1024), 0, stream, info, g, (uint32_t)W, dtype, forecaster,
+                       learn_shift, dst, out_size, status);
+    if (g.nseg > 0) {
+        const uint64_t units = stride / 16;
+        const uint32_t K = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(256, 2048 / units));
+        hipLaunchKernelGGL(spz::k_enc_compact, dim3((g.nseg + K - 1) / K), dim3(256), 0, stream, slots, stride, info,
+                           g, (uint32_t)W, K, dst, status);
+    }
+    return hipGetLastError();
 }
 
 template <int W, bool FIRE, bool COL>
@@ -230,9 +282,18 @@ size_t sprintz_compress_bound(uint64_t rows, uint32_t D, spz_dtype dtype, const 
     return total;
 }
 
+size_t sprintz_workspace_size_min(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
+    if (bits_of(dtype) == 0 || D == 0 || check_params(p) != SPZ_OK) return 0;
+    if (p->entropy == 1) return sprintz_workspace_size(rows, D, dtype, p);
+    return 8 * (size_t)num_segments(rows, p->seg_rows) + 8;
+}
+
 size_t sprintz_workspace_size(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
     if (bits_of(dtype) == 0 || D == 0 || check_params(p) != SPZ_OK) return 0;
     const uint64_t nseg = num_segments(rows, p->seg_rows);
+    const uint32_t w = bits_of(dtype);
+    if (p->entropy == 0 && p->hdr_group == 0 && D <= 16)
+        return std::max(sp_workspace_bytes(nseg, p->seg_rows, D, w), 8 * (size_t)nseg + 8);
     if (p->entropy == 1) {
         // plain container | its workspace | per-segment code records | plain size
         spz_params pp = *p;
@@ -289,7 +350,7 @@ spz_status sprintz_compress(const void *d_src, uint64_t rows, uint32_t D, spz_dt
         ((uintptr_t)d_out_size & 7))
         return SPZ_EINVAL;
     if (dst_cap < sprintz_compress_bound(rows, D, dtype, p)) return SPZ_ENOSPC;
-    if (ws_size < sprintz_workspace_size(rows, D, dtype, p)) return SPZ_ENOSPC;
+    if (ws_size < sprintz_workspace_size_min(rows, D, dtype, p)) return SPZ_ENOSPC;
     if (p->entropy == 1) return compress_entropy(d_src, rows, D, dtype, p, d_dst, dst_cap, d_out_size, d_ws, d_status,
                                                  stream);
     spz::Geom g = make_geom(rows, D, w, p->seg_rows, p->hdr_group, p->learn_shift);
@@ -299,6 +360,18 @@ spz_status sprintz_compress(const void *d_src, uint64_t rows, uint32_t D, spz_dt
     uint32_t *ws = (uint32_t *)d_ws;
     uint8_t *dst = (uint8_t *)d_dst;
     hipError_t e;
+    if (enc_sp_ok(g, w, d_src, d_ws) && ws_size >= sp_workspace_bytes(g.nseg, g.S, D, w)) {
+        uint8_t *wsb = (uint8_t *)d_ws;
+        if (w == 8) e = fire ? launch_encode_sp<8, true>(d_src, g, wsb, dst, d_status, (uint32_t)dtype, p->forecaster,
+                                                         p->learn_shift, d_out_size, stream)
+                             : launch_encode_sp<8, false>(d_src, g, wsb, dst, d_status, (uint32_t)dtype,
+                                                          p->forecaster, p->learn_shift, d_out_size, stream);
+        else e = fire ? launch_encode_sp<16, true>(d_src, g, wsb, dst, d_status, (uint32_t)dtype, p->forecaster,
+                                                   p->learn_shift, d_out_size, stream)
+                      : launch_encode_sp<16, false>(d_src, g, wsb, dst, d_status, (uint32_t)dtype, p->forecaster,
+                                                    p->learn_shift, d_out_size, stream);
+        return e == hipSuccess ? SPZ_OK : SPZ_EHIP;
+    }
 #define SPZ_ENC(W_, F_, C_) \
     launch_encode<W_, F_, C_>(d_src, g, ws, dst, d_status, (uint32_t)dtype, p->forecaster, p->learn_shift, d_out_size, stream)
     if (w == 8) {
@@ -318,7 +391,7 @@ spz_status sprintz_compress_noalloc(const void *d_src, uint64_t rows, uint32_t D
     // the same kernels as sprintz_compress, with the library's scratch array
     // as the workspace; every value the kernels read from it is written by
     // the same call first, so nothing needs clearing between calls
-    const size_t need = sprintz_workspace_size(rows, D, dtype, p);
+    const size_t need = sprintz_workspace_size_min(rows, D, dtype, p);
     if (need > kScratchBytes) return SPZ_ENOSPC;
     void *ws = nullptr;
     const spz_status st = scratch_address(&ws);

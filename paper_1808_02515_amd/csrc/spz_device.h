@@ -115,6 +115,10 @@ __device__ __forceinline__ void buf_st16(Buf b, uint32_t off, uint32_t v) {
     __builtin_amdgcn_raw_buffer_store_b16((uint16_t)v, b.r, off, 0, 0);
 }
 
+__device__ __forceinline__ void buf_st32(Buf b, uint32_t off, uint32_t v) {
+    __builtin_amdgcn_raw_buffer_store_b32(v, b.r, off, 0, 0);
+}
+
 __device__ __forceinline__ void buf_st128(Buf b, uint32_t off, u32x4 v) {
     __builtin_amdgcn_raw_buffer_store_b128(v, b.r, off, 0, 0);
 }

@@ -1,0 +1,618 @@
+// Single-pass Sprintz encoder for gfx950 (header group = whole segment,
+// D up to 16).
+//
+// Paper: Algorithm 1 (encodeBlock) for every 8-row block, the forecasters of
+// Section 4.2 (delta coding; FIRE with the practical changes of Section
+// 4.2.2: alpha once per block, one summed gradient update per block from
+// every other sample), zigzag residuals, per-column bit widths behind
+// log2(w)-bit headers and column- or row-major payloads (Section 4.3), runs
+// of all-zero blocks as run-length records (Algorithm 1).
+//
+// Compression has one serial dependence: FIRE's coefficient of block b+1
+// needs the residual signs of block b. A workgroup holds SPW = 64 / Dp
+// segments (64 column chains) and walks them in chunks of CB blocks with one
+// barrier per chunk:
+//   alpha wave (FIRE)  chunk t: lane = column chain, the coefficient chain
+//                      over the chunk's blocks (registers carry it on)
+//   item waves         chunk t-1 (t for delta): lanes = (segment, block,
+//                      column): deltas, residuals, zigzag codes and the
+//                      column's bit width; DPP sums over the columns of a
+//                      block give bit offsets, the record's header code word
+//                      and its payload size. Lanes = (segment, block) then
+//                      scan the chunk's records (run-length records, record
+//                      indices, payload byte offsets). Fields and header
+//                      codes are OR-ed into per-segment LDS staging; whole
+//                      16-byte units (whole header dwords) go out, the
+//                      partial last one stays for the next chunk.
+//   item waves also    16-byte loads of chunk t+1's rows into registers,
+//                      stored to LDS staging after the chunk's work.
+// A wave tile (64 item lanes) covers whole segment-chunks, so the record
+// scans and the staging flushes are wave-local: the only workgroup barrier
+// is the one per chunk.
+//
+// Every segment goes to a slot of the workspace: the u32 record count and
+// the header array from byte 0, the payload and the raw tail rows from byte
+// P0 (the largest header, rounded up). Its sizes go to a 16-byte info record;
+// k_enc_scan turns the sizes into the offset table and k_enc_compact copies
+// each segment to its place in the container. The input is read once.
+//
+// Global accesses go through buffer resources bounded to the workgroup's
+// input rows, its workspace slots and (compaction) its part of the container.
+#pragma once
+
+#include "spz_decode_pc.h"
+#include "spz_device.h"
+
+namespace spz {
+
+constexpr int kEsItemWaves = 4;
+
+// Inclusive max over an aligned group of N <= 16 lanes (values >= 0).
+template <int N> __device__ __forceinline__ uint32_t es_incl_max(uint32_t v, uint32_t i) {
+    if constexpr (N >= 2) { const uint32_t t = pc_dpp<0x111>(v); v = i >= 1 ? max(v, t) : v; }
+    if constexpr (N >= 4) { const uint32_t t = pc_dpp<0x112>(v); v = i >= 2 ? max(v, t) : v; }
+    if constexpr (N >= 8) { const uint32_t t = pc_dpp<0x114>(v); v = i >= 4 ? max(v, t) : v; }
+    if constexpr (N >= 16) { const uint32_t t = pc_dpp<0x118>(v); v = i >= 8 ? max(v, t) : v; }
+    return v;
+}
+
+// The value of lane i-1 of an aligned group (0 in the group's first lane).
+__device__ __forceinline__ uint32_t es_prev(uint32_t v, uint32_t i) {
+    const uint32_t t = pc_dpp<0x111>(v);   // row_shr:1
+    return i >= 1 ? t : 0u;
+}
+
+template <int W, int D> struct EsGeom {
+    static constexpr uint32_t HB = W == 8 ? 3 : 4;
+    static constexpr uint32_t WB = W / 8;
+    static constexpr uint32_t DP = pc_pow2(D);                     // item lanes per block
+    static constexpr uint32_t SPW = 64 / DP;                       // segments per workgroup
+    static constexpr uint32_t CB = DP <= 8 ? 8 : 64 / DP;          // blocks per chunk
+    static constexpr uint32_t CR = 8 * CB;                         // rows per chunk
+    static constexpr uint32_t SEGB = CR * D * WB;                  // staged bytes of a segment-chunk
+    static constexpr uint32_t SSTR = SEGB + 16;                    // their LDS stride (bank spread)
+    static constexpr uint32_t UNITS = SEGB / 16;                   // 16-byte input units
+    static constexpr uint32_t SPT = 64 / (CB * DP);                // segments per wave tile
+    static constexpr uint32_t NBS = 64 / DP;                       // block slots per wave tile
+    static constexpr uint32_t PASSES = CB / kEsItemWaves;          // wave tiles per item wave
+    static constexpr uint32_t MAXBLK = 8 * D * WB;                 // largest block payload
+    // Records in one chunk of one segment: its nonzero blocks, the runs
+    // between them, and the pieces of a run carried in from earlier chunks
+    // (a segment has at most 2^17 blocks, so at most 3 pieces of 65,535).
+    static constexpr uint32_t MAXREC = CB + 4;
+    // payload staging per segment: the carried partial unit, one chunk of
+    // payloads and run records; at the segment's end the trailing run
+    // records and the raw tail rows
+    static constexpr uint32_t PBYTES = 16 + CB * MAXBLK + 2 * MAXREC + 7 * D * WB;
+    static constexpr uint32_t PUNITS = (PBYTES + 15) / 16;
+    static constexpr uint32_t PSTR = PUNITS * 4;                   // dwords
+    // header staging: the carried partial dword and one chunk of records
+    static constexpr uint32_t HSTR = (32 + MAXREC * D * HB + 31) / 32 + 1;   // dwords
+    static constexpr uint32_t NT = 64 * (kEsItemWaves + 1);
+    static_assert(SEGB % 16 == 0 && CB % kEsItemWaves == 0 && SPT >= 1 && SPT * CB * DP == 64, "geometry");
+};
+
+// Largest header array of a segment with nblk blocks, and the slot layout.
+__host__ __device__ inline uint64_t es_hdr_cap(uint64_t nblk, uint32_t D, uint32_t w) {
+    return (nblk * D * (w == 8 ? 3u : 4u) + 7) / 8;
+}
+__host__ __device__ inline uint64_t es_p0(uint64_t nblk, uint32_t D, uint32_t w) {
+    return (4 + es_hdr_cap(nblk, D, w) + 4 + 15) & ~15ull;
+}
+__host__ __device__ inline uint64_t es_slot_bytes(uint64_t nblk, uint32_t D, uint32_t w) {
+    // full-width payloads, run records of a segment, raw tail rows, and the
+    // whole last staged unit
+    return (es_p0(nblk, D, w) + nblk * D * w + 8 + 7ull * D * (w / 8) + 32 + 15) & ~15ull;
+}
+
+// Per-segment encoding state in LDS.
+struct EsSeg {
+    uint32_t nblk, tail;      // whole blocks, raw tail rows
+    uint32_t r, cursor, run;  // records so far, payload bytes so far, zero blocks pending
+    uint32_t pad0, pad1, pad2;
+};
+
+template <int W, bool FIRE, int D>
+__global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uint8_t *__restrict__ src, Geom g,
+                                                               uint8_t *__restrict__ slots, uint64_t slot_stride,
+                                                               u32x4 *__restrict__ info) {
+    using G = EsGeom<W, D>;
+    constexpr uint32_t HB = G::HB, WB = G::WB, DP = G::DP, SPW = G::SPW, CB = G::CB, CR = G::CR;
+    constexpr uint32_t SSTR = G::SSTR, SPT = G::SPT, PSTR = G::PSTR, HSTR = G::HSTR, NBS = G::NBS;
+    constexpr uint32_t PUNITS = G::PUNITS;
+    constexpr bool COL = D * W <= 32;   // column-major payloads (reading R13)
+    constexpr uint32_t NBUF = FIRE ? 3 : 2;
+    constexpr uint32_t LAG = FIRE ? 1 : 0;   // item waves work one chunk behind the alpha wave
+
+    __shared__ u32x4 STG[NBUF * SPW * SSTR / 16];          // staged rows: [buffer][segment][row][column]
+    __shared__ int32_t ALPHA[FIRE ? 2 * 64 * CB : 1];       // [parity][chain][block]
+    __shared__ uint32_t PREVX[2][64];                       // a chain's last sample before the chunk
+    __shared__ int32_t PREVD[2][64];                        // and its last delta
+    __shared__ u32x4 PST4[SPW * PSTR / 4];                  // payload staging per segment
+    __shared__ uint32_t HST[SPW * HSTR];                    // header staging per segment
+    __shared__ u32x4 BLK[kEsItemWaves][64];                 // wave-local block records
+    __shared__ EsSeg SEG[SPW];
+    uint32_t *const PST = reinterpret_cast<uint32_t *>(PST4);
+    const uint8_t *const stgb = reinterpret_cast<const uint8_t *>(STG);
+
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const bool alpha_wave = wave == kEsItemWaves;
+    const uint32_t seg0 = blockIdx.x * SPW;
+    const uint32_t nsw = min(SPW, g.nseg - seg0);
+
+    // bounded views: this workgroup's input rows and its workspace slots
+    const uint64_t wrow0 = (uint64_t)seg0 * g.S;
+    const uint64_t wrows = min((uint64_t)nsw * g.S, g.rows - wrow0);
+    const uint32_t in_bytes = (uint32_t)(wrows * D * WB);
+    const Buf in = make_buf(src + wrow0 * D * WB, in_bytes);
+    const uint32_t sstride = (uint32_t)slot_stride;
+    const Buf out = make_buf(slots + (uint64_t)seg0 * slot_stride, nsw * sstride);
+    const uint32_t p0 = (uint32_t)es_p0(g.S >> 3, D, W);
+
+    // ---- setup ------------------------------------------------------------------
+    if (tid < SPW) {
+        EsSeg sg;
+        const uint32_t nr = tid < nsw ? (uint32_t)min((uint64_t)g.S, g.rows - (uint64_t)(seg0 + tid) * g.S) : 0u;
+        sg.nblk = nr >> 3;
+        sg.tail = nr & 7u;
+        sg.r = 0; sg.cursor = 0; sg.run = 0; sg.pad0 = 0; sg.pad1 = 0; sg.pad2 = 0;
+        SEG[tid] = sg;
+    }
+    for (uint32_t k = tid; k < SPW * PSTR; k += G::NT) PST[k] = 0;
+    for (uint32_t k = tid; k < SPW * HSTR; k += G::NT) HST[k] = 0;
+    if (tid < 64) { PREVX[0][tid] = 0; PREVD[0][tid] = 0; }
+
+    // staging of a chunk's rows: 16-byte units over the item lanes
+    constexpr uint32_t NIT = 64 * kEsItemWaves;
+    constexpr uint32_t SUN = (SPW * G::UNITS + NIT - 1) / NIT;
+    u32x4 reg[SUN];
+    auto stage_issue = [&](uint32_t c) {
+#pragma unroll
+        for (uint32_t t = 0; t < SUN; ++t) {
+            const uint32_t u = tid + t * NIT;
+            const uint32_t s = u / G::UNITS, k = u % G::UNITS;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (u < SPW * G::UNITS && s < nsw) {
+                const uint32_t off = (s * g.S + c * CR) * D * WB + 16 * k;
+                if (off + 16 <= in_bytes) {
+                    v = buf_ld128(in, off);
+                } else if (off < in_bytes) {
+                    // a unit across the end of the input (rows end on 8-byte
+                    // boundaries at least, so its dwords are whole or absent)
+                    v.x = buf_ld32(in, off);
+                    v.y = buf_ld32(in, off + 4);
+                    v.z = buf_ld32(in, off + 8);
+                    v.w = buf_ld32(in, off + 12);
+                }
+            }
+            reg[t] = v;
+        }
+    };
+    auto stage_commit = [&](uint32_t c) {
+        u32x4 *const dstg = STG + (c % NBUF) * (SPW * SSTR / 16);
+#pragma unroll
+        for (uint32_t t = 0; t < SUN; ++t) {
+            const uint32_t u = tid + t * NIT;
+            const uint32_t s = u / G::UNITS, k = u % G::UNITS;
+            if (u < SPW * G::UNITS) dstg[s * (SSTR / 16) + k] = reg[t];
+        }
+    };
+    auto xval = [&](uint32_t buf, uint32_t s, uint32_t row, uint32_t j) -> uint32_t {
+        const uint32_t off = (buf * SPW + s) * SSTR + (row * D + j) * WB;
+        return WB == 1 ? (uint32_t)stgb[off] : (uint32_t)*reinterpret_cast<const uint16_t *>(stgb + off);
+    };
+
+    if (!alpha_wave) {
+        stage_issue(0);
+        stage_commit(0);
+    }
+    __syncthreads();
+
+    const uint32_t nchunks = ((g.S >> 3) + CB - 1) / CB;
+
+    // alpha wave state: one column chain per lane
+    const uint32_t a_s = lane / DP, a_j = lane % DP;
+    const bool a_on = alpha_wave && a_j < (uint32_t)D && a_s < nsw;
+    uint32_t a_x = 0;
+    int32_t a_d = 0, acc = 0;
+
+    for (uint32_t t = 0; t < nchunks + LAG; ++t) {
+        if (alpha_wave) {
+            if (FIRE && t < nchunks && a_on) {
+                // ---- the coefficient chain over chunk t ------------------------
+                const uint32_t buf = t % NBUF;
+                const uint32_t nb = SEG[a_s].nblk;
+                const uint32_t bic = t * CB < nb ? min(CB, nb - t * CB) : 0u;
+                for (uint32_t b = 0; b < bic; ++b) {
+                    uint32_t xs[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) xs[i] = xval(buf, a_s, 8 * b + i, a_j);
+                    const int32_t alpha = acc >> g.sh;
+                    ALPHA[((t & 1) * 64 + lane) * CB + b] = alpha;
+                    int32_t grad = 0;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int32_t d = sext<W>((int32_t)(xs[i] - a_x));
+                        if (i & 1) {
+                            const int32_t e = sext<W>(d - (__mul24(alpha, a_d) >> W));
+                            grad += __mul24(sgn_med3(e), a_d);
+                        }
+                        a_d = d;
+                        a_x = xs[i];
+                    }
+                    acc = min(max(acc + grad, g.acc_lo), g.acc_hi);
+                }
+            }
+        } else {
+            if (t + 1 < nchunks) stage_issue(t + 1);
+            if (t >= LAG) {
+                const uint32_t c = t - LAG;
+                const uint32_t buf = c % NBUF;
+#pragma unroll
+                for (uint32_t pass = 0; pass < G::PASSES; ++pass) {
+                    const uint32_t tile = pass * kEsItemWaves + wave;
+                    // ---- item lanes: (segment, block, column) ----------------------
+                    const uint32_t sl = lane / (CB * DP), b = (lane / DP) % CB, j = lane % DP;
+                    const uint32_t s = tile * SPT + sl;
+                    const uint32_t nblk_s = SEG[s].nblk;
+                    const uint32_t bic = c * CB < nblk_s ? min(CB, nblk_s - c * CB) : 0u;
+                    const bool valid = s < nsw && b < bic;
+                    const bool act = valid && j < (uint32_t)D;
+                    const uint32_t ch = s * DP + j;
+                    uint32_t z[8];
+                    uint32_t orz = 0;
+                    if (act) {
+                        uint32_t xp = b == 0 ? PREVX[c & 1][ch] : xval(buf, s, 8 * b - 1, j);
+                        int32_t dp = 0;
+                        if (FIRE) dp = b == 0 ? PREVD[c & 1][ch] : sext<W>((int32_t)(xp - xval(buf, s, 8 * b - 2, j)));
+                        const int32_t alpha = FIRE ? ALPHA[((c & 1) * 64 + ch) * CB + b] : 0;
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const uint32_t x = xval(buf, s, 8 * b + i, j);
+                            const int32_t d = sext<W>((int32_t)(x - xp));
+                            const int32_t e = FIRE ? sext<W>(d - (__mul24(alpha, dp) >> W)) : d;
+                            z[i] = zigzag(e);
+                            orz |= z[i];
+                            dp = d;
+                            xp = x;
+                        }
+                        if (b == bic - 1) {
+                            PREVX[(c + 1) & 1][ch] = xp;
+                            PREVD[(c + 1) & 1][ch] = dp;
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) z[i] = 0;
+                    }
+                    const uint32_t code = min(bitlen(orz), (uint32_t)W - 1);
+                    const uint32_t width = code < (uint32_t)W - 1 ? code : (uint32_t)W;
+                    const uint32_t wsum = pc_total<DP>(width);
+                    const uint32_t off = pc_incl<DP>(width, j) - width;
+                    // header code word of the block: D fields of HB bits, LSB first
+                    const uint32_t cb0 = j * HB;
+                    const uint32_t cw_lo = pc_total<DP>(cb0 < 32 ? code << cb0 : 0u);
+                    uint32_t cw_hi = 0;
+                    if constexpr (D * HB > 32)
+                        cw_hi = pc_total<DP>(cb0 + HB <= 32 ? 0u : cb0 >= 32 ? code << (cb0 - 32) : code >> (32 - cb0));
+                    const uint32_t bslot = lane / DP;
+                    if (j == 0) {
+                        u32x4 v;
+                        v.x = wsum; v.y = cw_lo; v.z = cw_hi; v.w = valid ? 1u : 0u;
+                        BLK[wave][bslot] = v;
+                    }
+                    wave_sync();
+                    // ---- block lanes: (segment, block); records of the chunk ---------
+                    if (lane < NBS) {
+                        const uint32_t bs = lane, bb = bs % CB;
+                        const uint32_t ss = tile * SPT + bs / CB;
+                        const EsSeg q = SEG[ss];
+                        const u32x4 bv = BLK[wave][bs];
+                        const bool nz = bv.w != 0 && bv.x != 0;
+                        const uint32_t qbic = c * CB < q.nblk ? min(CB, q.nblk - c * CB) : 0u;
+                        // last nonzero block up to this one, 1-based (0 = none)
+                        const uint32_t lastin = es_incl_max<CB>(nz ? bb + 1 : 0u, bb);
+                        const uint32_t prevnz = es_prev(lastin, bb);
+                        const uint32_t run = !nz ? 0u : prevnz == 0 ? q.run + bb : bb - prevnz;
+                        const uint32_t nrle = (run + kRleMax - 1) / kRleMax;
+                        const uint32_t psize = COL ? bv.x : 8 * ((bv.x + 7) >> 3);
+                        const uint32_t nrec_b = nz ? nrle + 1 : 0u;
+                        const uint32_t pay_b = nz ? 2 * nrle + psize : 0u;
+                        const uint32_t rinc = pc_incl<CB>(nrec_b, bb);
+                        const uint32_t pinc = pc_incl<CB>(pay_b, bb);
+                        const uint32_t nrec_c = pc_total<CB>(nrec_b);
+                        const uint32_t pay_c = pc_total<CB>(pay_b);
+                        const uint32_t lastall = pc_total<CB>(bb == CB - 1 ? lastin : 0u);
+                        const uint32_t prun = q.cursor + pinc - pay_b;   // its run records
+                        const uint32_t pbase = q.cursor & ~15u;
+                        // run records before the block: u16 counts in the payload staging
+                        uint8_t *const pb = reinterpret_cast<uint8_t *>(PST + ss * PSTR);
+                        for (uint32_t k = 0; k < nrle; ++k) {
+                            const uint32_t cnt = k + 1 < nrle ? kRleMax : run - kRleMax * (nrle - 1);
+                            const uint32_t at = prun + 2 * k - pbase;
+                            pb[at] = (uint8_t)cnt;
+                            pb[at + 1] = (uint8_t)(cnt >> 8);
+                        }
+                        wave_sync();
+                        u32x4 res;
+                        res.x = q.r + rinc - 1;    // record index of the block
+                        res.y = prun + 2 * nrle;   // payload byte of the block
+                        res.z = q.r;               // records before the chunk
+                        res.w = q.cursor;          // payload bytes before the chunk
+                        BLK[wave][bs] = res;
+                        if (bb == 0 && ss < nsw && qbic > 0) {
+                            EsSeg &ns = SEG[ss];
+                            ns.r = q.r + nrec_c;
+                            ns.cursor = q.cursor + pay_c;
+                            ns.run = lastall == 0 ? q.run + qbic : qbic - lastall;
+                        }
+                    } else {
+                        wave_sync();
+                    }
+                    wave_sync();
+                    // ---- pack: fields and header codes into the staging ---------------
+                    {
+                        const u32x4 res = BLK[wave][bslot];
+                        if (valid && wsum != 0) {
+                            const uint32_t pbase = res.w & ~15u;
+                            uint32_t *const pw = PST + s * PSTR;
+                            const uint32_t pbit = 8 * (res.y - pbase);
+                            const uint32_t rbits = 8 * ((wsum + 7) >> 3);
+                            if (act && width != 0) {
+#pragma unroll
+                                for (int i = 0; i < 8; ++i) {
+                                    const uint32_t p = COL ? pbit + 8 * off + (uint32_t)i * width
+                                                           : pbit + (uint32_t)i * rbits + off;
+                                    const uint32_t sb = p & 31u;
+                                    atomicOr(&pw[p >> 5], z[i] << sb);
+                                    if (sb + width > 32) atomicOr(&pw[(p >> 5) + 1], z[i] >> (32 - sb));
+                                }
+                            }
+                            if (j == 0) {
+                                const uint32_t hb0 = (res.z * D * HB) & ~31u;
+                                const uint32_t lb = res.x * D * HB - hb0;
+                                uint32_t *const hw = HST + s * HSTR + (lb >> 5);
+                                const uint32_t sb = lb & 31u;
+                                if (cw_lo) atomicOr(&hw[0], cw_lo << sb);
+                                if constexpr (D * HB > 32) {
+                                    const uint32_t w1 = (sb ? cw_lo >> (32 - sb) : 0u) | (cw_hi << sb);
+                                    if (w1) atomicOr(&hw[1], w1);
+                                    if (sb && (cw_hi >> (32 - sb))) atomicOr(&hw[2], cw_hi >> (32 - sb));
+                                } else {
+                                    if (sb + D * HB > 32 && (cw_lo >> (32 - sb))) atomicOr(&hw[1], cw_lo >> (32 - sb));
+                                }
+                            }
+                        }
+                    }
+                    wave_sync();
+                    // ---- flush: whole units and header dwords out, the rest stays ------
+                    constexpr uint32_t FP = (SPT * PUNITS + 63) / 64;
+                    constexpr uint32_t FH = (SPT * HSTR + 63) / 64;
+                    u32x4 pcarry[FP];
+                    uint32_t hcarry[FH];
+#pragma unroll
+                    for (uint32_t k = 0; k < FP; ++k) {
+                        const uint32_t f = lane + 64 * k;
+                        const uint32_t fs = f / PUNITS, u = f % PUNITS;
+                        const uint32_t ss = tile * SPT + fs;
+                        pcarry[k] = u32x4{0u, 0u, 0u, 0u};
+                        if (f < SPT * PUNITS && ss < nsw) {
+                            const uint32_t pbase = BLK[wave][fs * CB].w & ~15u;
+                            const uint32_t nfull = (SEG[ss].cursor - pbase) >> 4;
+                            const u32x4 *const pu = PST4 + ss * (PSTR / 4);
+                            if (u < nfull) buf_st128(out, ss * sstride + p0 + pbase + 16 * u, pu[u]);
+                            if (u == 0) pcarry[k] = pu[nfull];
+                        }
+                    }
+#pragma unroll
+                    for (uint32_t k = 0; k < FH; ++k) {
+                        const uint32_t f = lane + 64 * k;
+                        const uint32_t fs = f / HSTR, qd = f % HSTR;
+                        const uint32_t ss = tile * SPT + fs;
+                        hcarry[k] = 0;
+                        if (f < SPT * HSTR && ss < nsw) {
+                            const uint32_t hb0 = (BLK[wave][fs * CB].z * D * HB) & ~31u;
+                            const uint32_t hfull = (SEG[ss].r * D * HB - hb0) >> 5;
+                            const uint32_t *const hw = HST + ss * HSTR;
+                            if (qd < hfull) buf_st32(out, ss * sstride + 4 + hb0 / 8 + 4 * qd, hw[qd]);
+                            if (qd == 0) hcarry[k] = hw[hfull];
+                        }
+                    }
+                    wave_sync();
+#pragma unroll
+                    for (uint32_t k = 0; k < FP; ++k) {
+                        const uint32_t f = lane + 64 * k;
+                        const uint32_t fs = f / PUNITS, u = f % PUNITS;
+                        const uint32_t ss = tile * SPT + fs;
+                        if (f < SPT * PUNITS && ss < nsw) {
+                            const uint32_t pbase = BLK[wave][fs * CB].w & ~15u;
+                            const uint32_t nused = (SEG[ss].cursor - pbase + 15) >> 4;
+                            if (u == 0 || u < nused) PST4[ss * (PSTR / 4) + u] = u == 0 ? pcarry[k] : u32x4{0u, 0u, 0u, 0u};
+                        }
+                    }
+#pragma unroll
+                    for (uint32_t k = 0; k < FH; ++k) {
+                        const uint32_t f = lane + 64 * k;
+                        const uint32_t fs = f / HSTR, qd = f % HSTR;
+                        const uint32_t ss = tile * SPT + fs;
+                        if (f < SPT * HSTR && ss < nsw) HST[ss * HSTR + qd] = qd == 0 ? hcarry[k] : 0u;
+                    }
+                    wave_sync();
+                }
+            }
+            if (t + 1 < nchunks) stage_commit(t + 1);
+        }
+        __syncthreads();
+    }
+
+    // ---- segment ends: trailing runs, raw tail rows, last units, sizes ----------
+    if (!alpha_wave) {
+#pragma unroll
+        for (uint32_t pass = 0; pass < G::PASSES; ++pass) {
+            const uint32_t tile = pass * kEsItemWaves + wave;
+            for (uint32_t fs = 0; fs < SPT; ++fs) {
+                const uint32_t ss = tile * SPT + fs;
+                if (ss >= nsw) break;
+                const EsSeg q = SEG[ss];
+                const uint32_t pbase = q.cursor & ~15u;
+                const uint32_t nrle = (q.run + kRleMax - 1) / kRleMax;
+                uint8_t *const pb = reinterpret_cast<uint8_t *>(PST + ss * PSTR);
+                if (lane < nrle) {
+                    const uint32_t cnt = lane + 1 < nrle ? kRleMax : q.run - kRleMax * (nrle - 1);
+                    const uint32_t at = q.cursor + 2 * lane - pbase;
+                    pb[at] = (uint8_t)cnt;
+                    pb[at + 1] = (uint8_t)(cnt >> 8);
+                }
+                const uint32_t tb = q.tail * D * WB;
+                const uint32_t tpos = q.cursor + 2 * nrle;
+                const uint32_t trow = (ss * g.S + q.nblk * 8) * D * WB;   // in the workgroup's input
+                for (uint32_t k = lane; k < tb; k += 64) pb[tpos - pbase + k] = (uint8_t)buf_ld8(in, trow + k);
+                wave_sync();
+                const uint32_t paytail = tpos + tb;
+                const uint32_t nunits = (paytail - pbase + 15) >> 4;
+                for (uint32_t u = lane; u < nunits; u += 64)
+                    buf_st128(out, ss * sstride + p0 + pbase + 16 * u, PST4[ss * (PSTR / 4) + u]);
+                const uint32_t nrec = q.r + nrle;
+                const uint32_t hbits = nrec * D * HB;
+                const uint32_t hb0 = (q.r * D * HB) & ~31u;
+                const uint32_t ndw = (hbits - hb0 + 31) >> 5;
+                for (uint32_t k = lane; k < ndw; k += 64)
+                    buf_st32(out, ss * sstride + 4 + hb0 / 8 + 4 * k, HST[ss * HSTR + k]);
+                if (lane == 0) {
+                    buf_st32(out, ss * sstride, nrec);
+                    const uint32_t hdr = (hbits + 7) >> 3;
+                    u32x4 v;
+                    v.x = (4 + hdr + paytail + 15) & ~15u;   // segment bytes
+                    v.y = nrec;
+                    v.z = paytail;                           // payload and tail bytes
+                    v.w = 0;
+                    info[seg0 + ss] = v;
+                }
+            }
+        }
+    }
+}
+
+// Offset table and container header from the segment sizes (one workgroup):
+// each thread sums a contiguous run of segments, one block scan, then the
+// table entries of its run.
+__global__ __launch_bounds__(1024) void k_enc_scan(const u32x4 *__restrict__ info, Geom g, uint32_t w, uint32_t dtype,
+                                                   uint32_t forecaster, uint32_t learn_shift, uint8_t *__restrict__ dst,
+                                                   uint64_t *__restrict__ out_size, int32_t *__restrict__ status) {
+    __shared__ uint64_t wsum[16];
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint32_t n = g.nseg;
+    const uint32_t per = (n + 1023) / 1024;
+    const uint32_t k0 = min(n, t * per), k1 = min(n, k0 + per);
+    uint64_t mine = 0;
+    for (uint32_t k = k0; k < k1; ++k) mine += info[k].x;
+    uint64_t incl = mine;
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint64_t o = (uint64_t)__shfl_up((unsigned long long)incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    uint64_t before = 0, total = 0;
+    for (uint32_t q = 0; q < 16; ++q) {
+        const uint64_t v = wsum[q];
+        if (q < wv) before += v;
+        total += v;
+    }
+    uint64_t *tab = reinterpret_cast<uint64_t *>(dst + 64);
+    uint64_t run = before + incl - mine;
+    for (uint32_t k = k0; k < k1; ++k) {
+        tab[k] = run;
+        run += info[k].x;
+    }
+    if (t == 0) tab[n] = total;
+    if (t < 16) {
+        // 64-byte header as 16 dwords (reading R18: the container layout)
+        uint32_t word = 0;
+        switch (t) {
+            case 0: word = 0x315A5053u; break;                                            // "SPZ1"
+            case 1: word = 1u | (w << 16) | (dtype << 24); break;                          // version, w, dtype
+            case 2: word = forecaster | (learn_shift << 8) | (g.G << 16); break;           // entropy 0
+            case 3: word = g.D; break;
+            case 4: word = (uint32_t)g.rows; break;
+            case 5: word = (uint32_t)(g.rows >> 32); break;
+            case 6: word = g.S; break;
+            case 7: word = n; break;
+            case 8: word = (uint32_t)total; break;
+            case 9: word = (uint32_t)(total >> 32); break;
+            default: word = 0; break;
+        }
+        reinterpret_cast<uint32_t *>(dst)[t] = word;
+    }
+    // zero padding between the offset table and the data
+    const uint64_t pad0 = 64 + 8ull * (n + 1);
+    if (t < g.data_start - pad0) dst[pad0 + t] = 0;
+    if (t == 0) {
+        *out_size = g.data_start + total;
+        if (g.data_start + total > g.cap && status) atomicOr(status, 2);
+    }
+}
+
+// Copies K segments per workgroup from their workspace slots to the
+// container: destination units of 16 bytes, bytes [0, 4 + header) from the
+// slot's start and the rest from its payload at P0, zero padding at the end.
+__global__ __launch_bounds__(256) void k_enc_compact(const uint8_t *__restrict__ slots, uint64_t slot_stride,
+                                                     const u32x4 *__restrict__ info, Geom g, uint32_t w,
+                                                     uint32_t K, uint8_t *__restrict__ dst,
+                                                     int32_t *__restrict__ status) {
+    const uint32_t first = blockIdx.x * K;
+    if (first >= g.nseg) return;
+    const uint32_t last = min(g.nseg, first + K);
+    const uint64_t *tab = reinterpret_cast<const uint64_t *>(dst + 64);
+    const uint64_t o0 = tab[first], o1 = tab[last];
+    if (g.data_start + o1 > g.cap || o1 < o0 || o1 - o0 > 0xFFFFFFF0ull) {
+        if (threadIdx.x == 0 && status) atomicOr(status, 2);
+        return;
+    }
+    const Buf sb = make_buf(slots + (uint64_t)first * slot_stride, (uint32_t)((last - first) * slot_stride));
+    const Buf db = make_buf(dst + g.data_start + o0, (uint32_t)(o1 - o0));
+    const uint32_t hb = w == 8 ? 3u : 4u;
+    const uint32_t p0 = (uint32_t)es_p0(g.S >> 3, g.D, w);
+    for (uint32_t s = first; s < last; ++s) {
+        const u32x4 in = info[s];
+        const uint32_t size = in.x, A = 4 + (uint32_t)(((uint64_t)in.y * g.D * hb + 7) >> 3), PT = in.z;
+        const uint32_t sbase = (s - first) * (uint32_t)slot_stride;
+        const uint32_t dbase = (uint32_t)(tab[s] - o0);
+        if (size % 16 || size > slot_stride || A + PT > size || tab[s + 1] - tab[s] != size) {
+            if (threadIdx.x == 0 && status) atomicOr(status, 2);   // sizes that the encoder did not write
+            continue;
+        }
+        const uint32_t shift = 8 * ((p0 - A) & 3u);
+        for (uint32_t u = threadIdx.x; u < size / 16; u += blockDim.x) {
+            const uint32_t k0 = 16 * u;
+            u32x4 a = {0u, 0u, 0u, 0u};
+            if (k0 < A) a = buf_ld128(sb, sbase + k0);
+            uint32_t bw[5] = {0u, 0u, 0u, 0u, 0u};
+            if (k0 + 16 > A) {
+                // payload bytes for this unit start at slot byte P0 + k0 - A
+                // (below P0 for the unit that holds the header's end; those
+                // bytes are masked)
+                const uint32_t sbyte = p0 + k0 - A;
+                const uint32_t d0 = sbase + (sbyte & ~3u);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) bw[q] = buf_ld32(sb, d0 + 4 * q);
+            }
+            uint32_t v[4];
+            const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t kq = k0 + 4 * q;
+                const uint32_t bq = __builtin_amdgcn_alignbit(bw[q + 1], bw[q], shift);
+                const uint32_t na = A > kq ? min(A - kq, 4u) : 0u;         // bytes from the header part
+                const uint32_t nk = A + PT > kq ? min(A + PT - kq, 4u) : 0u;   // bytes that are not padding
+                const uint32_t ma = na >= 4 ? ~0u : (1u << (8 * na)) - 1u;
+                const uint32_t mk = nk >= 4 ? ~0u : (1u << (8 * nk)) - 1u;
+                v[q] = ((aw[q] & ma) | (bq & ~ma)) & mk;
+            }
+            u32x4 o;
+            o.x = v[0]; o.y = v[1]; o.z = v[2]; o.w = v[3];
+            buf_st128(db, dbase + k0, o);
+        }
+    }
+}
+
+}  // namespace spz

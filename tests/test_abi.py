@@ -56,7 +56,15 @@ def test_bound_matches_oracle_bound(lib, dt, code):
     for rows, D, S, G in [(0, 3, 8, 0), (7, 1, 8, 0), (65536, 1, 1024, 0), (100003, 8, 512, 2), (1000, 64, 64, 1)]:
         p = spz.make_params("fire", S, G)
         assert spz.sprintz_compress_bound(rows, D, code, p) == oracle.compress_bound(rows, D, dt, S, G)
-        assert spz.sprintz_workspace_size(rows, D, code, p) == 8 * (-(-rows // S)) + 8
+        nseg = -(-rows // S)
+        assert spz.sprintz_workspace_size_min(rows, D, code, p) == 8 * nseg + 8
+        ws = spz.sprintz_workspace_size(rows, D, code, p)
+        if G == 0 and D <= 16:
+            # the single-pass encoder: a slot of at least the segment's bound per segment
+            one = oracle.compress_bound(min(rows, S), D, dt, S, G) - oracle.compress_bound(0, D, dt, S, G)
+            assert ws >= nseg * one + 16 * nseg
+        else:
+            assert ws == 8 * nseg + 8
 
 
 def test_get_info_parses_oracle_container(lib):

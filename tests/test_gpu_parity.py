@@ -200,3 +200,38 @@ def test_corrupt_containers_flag_status_and_stay_in_bounds(D):
             bad[p] = int(rng.integers(0, 256))
         _say(f"corrupt: random #{k}")
         run(bad)
+
+
+def _gpu_compress_ws(x, f, S, ws_size_fn) -> bytes:
+    """Compress through the C ABI with the workspace size that ws_size_fn gives."""
+    rows, D = x.shape
+    code = {np.dtype(np.int8): spz.SPZ_INT8, np.dtype(np.uint8): spz.SPZ_UINT8,
+            np.dtype(np.int16): spz.SPZ_INT16, np.dtype(np.uint16): spz.SPZ_UINT16}[x.dtype]
+    p = spz.make_params(f, S)
+    cap = spz.sprintz_compress_bound(rows, D, code, p)
+    wsz = ws_size_fn(rows, D, code, p)
+    xd = _to_dev(x)
+    dst = torch.zeros(cap, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(max(wsz, 16), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rc = spz.sprintz_compress(xd.data_ptr(), rows, D, code, p, dst.data_ptr(), cap, out.data_ptr(), ws.data_ptr(),
+                              wsz, st.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    assert rc == spz.SPZ_OK, rc
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    return dst[: int(out.item())].cpu().numpy().tobytes()
+
+
+@pytest.mark.parametrize("f", ["delta", "fire"])
+def test_both_encoders_give_the_oracle_bytes(f):
+    # the single-pass encoder (full workspace) and the two-pass encoder
+    # (minimum workspace) on the same inputs
+    cases = [(datagen.ar2_uint16(70003, 8, seed=21), 1024), (datagen.walk_int8(30001, 1, seed=22), 512),
+             (datagen.ar2_uint16(9000, 3, seed=23).astype(np.int8), 64), (datagen.uniform(4099, 16, np.uint16, seed=24), 256),
+             (datagen.ar2_uint16(12345, 2, seed=25), 8)]
+    for x, S in cases:
+        _say(f"case two encoders f={f} shape={x.shape} dtype={x.dtype} S={S}")
+        ref = oracle.compress(x, f, S)
+        assert _gpu_compress_ws(x, f, S, spz.sprintz_workspace_size) == ref
+        assert _gpu_compress_ws(x, f, S, spz.sprintz_workspace_size_min) == ref

@@ -66,9 +66,15 @@ def _gpu():
 
 @pytest.mark.parametrize("f", ["fire", "delta"])
 def test_noalloc_equals_workspace_form_twice(f):
-    # first call: 131,075 x 8 uint16 rows (129 segments of 1024 rows and a
-    # ragged tail); second call: a smaller int8 stream over fewer segments
-    cases = [(datagen.ar2_uint16(131075, 8, seed=11), 1024), (datagen.walk_int8(20003, 1, seed=12), 512)]
+    # first call: 600,003 x 8 uint16 rows, whose single-pass workspace does
+    # not fit the static array (the two-pass encoder runs); then 131,075 x 8
+    # (129 segments, single pass) and a smaller int8 stream over fewer
+    # segments, each call smaller than the one before
+    big = datagen.ar2_uint16(600003, 8, seed=10)
+    p_big = spz.make_params(f, 1024)
+    assert spz.sprintz_workspace_size(600003, 8, spz.SPZ_UINT16, p_big) > spz.NOALLOC_WORKSPACE_BYTES
+    assert spz.sprintz_workspace_size(131075, 8, spz.SPZ_UINT16, p_big) <= spz.NOALLOC_WORKSPACE_BYTES
+    cases = [(big, 1024), (datagen.ar2_uint16(131075, 8, seed=11), 1024), (datagen.walk_int8(20003, 1, seed=12), 512)]
     for x, S in cases:
         rows, D = x.shape
         code = _dtype_code(x)
@@ -87,9 +93,9 @@ def test_noalloc_refuses_more_segments_than_its_workspace():
     # refused on the host (the pointers are never dereferenced)
     p = spz.make_params("fire", 8)
     rows = 524288 * 8
-    assert spz.sprintz_workspace_size(rows, 1, spz.SPZ_INT8, p) > spz.NOALLOC_WORKSPACE_BYTES
+    assert spz.sprintz_workspace_size_min(rows, 1, spz.SPZ_INT8, p) > spz.NOALLOC_WORKSPACE_BYTES
     fake = 1 << 20
     rc = spz.sprintz_compress_noalloc(fake, rows, 1, spz.SPZ_INT8, p, fake, 1 << 40, fake, 0, 0)
     assert rc == spz.SPZ_ENOSPC
     # one segment fewer fits
-    assert spz.sprintz_workspace_size(rows - 8, 1, spz.SPZ_INT8, p) <= spz.NOALLOC_WORKSPACE_BYTES
+    assert spz.sprintz_workspace_size_min(rows - 8, 1, spz.SPZ_INT8, p) <= spz.NOALLOC_WORKSPACE_BYTES
