@@ -109,30 +109,41 @@ __host__ __device__ inline uint64_t es_slot_bytes(uint64_t nblk, uint32_t D, uin
 struct EsSeg {
     uint32_t nblk, tail;      // whole blocks, raw tail rows
     uint32_t r, cursor, run;  // records so far, payload bytes so far, zero blocks pending
-    uint32_t pad0, pad1, pad2;
+    uint32_t r0, cursor0;     // the same at the start of the current chunk
+    uint32_t pad;
 };
+
+__host__ __device__ constexpr uint32_t es_pow2(uint32_t v) { return v <= 1 ? 1u : 2 * es_pow2((v + 1) / 2); }
 
 template <int W, bool FIRE, int D>
 __global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uint8_t *__restrict__ src, Geom g,
-                                                               uint8_t *__restrict__ slots, uint64_t slot_stride,
-                                                               u32x4 *__restrict__ info) {
+                                                                      uint8_t *__restrict__ slots,
+                                                                      uint64_t slot_stride,
+                                                                      u32x4 *__restrict__ info) {
     using G = EsGeom<W, D>;
     constexpr uint32_t HB = G::HB, WB = G::WB, DP = G::DP, SPW = G::SPW, CB = G::CB, CR = G::CR;
-    constexpr uint32_t SSTR = G::SSTR, SPT = G::SPT, PSTR = G::PSTR, HSTR = G::HSTR, NBS = G::NBS;
-    constexpr uint32_t PUNITS = G::PUNITS;
+    constexpr uint32_t SSTR = G::SSTR, SPT = G::SPT, NBS = G::NBS, P = G::PASSES;
     constexpr bool COL = D * W <= 32;   // column-major payloads (reading R13)
     constexpr uint32_t NBUF = FIRE ? 3 : 2;
     constexpr uint32_t LAG = FIRE ? 1 : 0;   // item waves work one chunk behind the alpha wave
+    // payload and header staging are rings (powers of two) over the
+    // segment's byte and header-bit positions: a unit goes out and is
+    // cleared as soon as it is complete, the partial last one stays in place
+    constexpr uint32_t PR = es_pow2(G::PUNITS);   // 16-byte units per segment
+    constexpr uint32_t HR = es_pow2(G::HSTR);     // header dwords per segment
+    constexpr uint32_t WSEG = SPT * P;            // segments of one item wave
+    constexpr uint32_t WSLOT = NBS * P;           // block slots of one item wave
 
     __shared__ u32x4 STG[NBUF * SPW * SSTR / 16];          // staged rows: [buffer][segment][row][column]
     __shared__ int32_t ALPHA[FIRE ? 2 * 64 * CB : 1];       // [parity][chain][block]
     __shared__ uint32_t PREVX[2][64];                       // a chain's last sample before the chunk
     __shared__ int32_t PREVD[2][64];                        // and its last delta
-    __shared__ u32x4 PST4[SPW * PSTR / 4];                  // payload staging per segment
-    __shared__ uint32_t HST[SPW * HSTR];                    // header staging per segment
-    __shared__ u32x4 BLK[kEsItemWaves][64];                 // wave-local block records
+    __shared__ u32x4 PST4[SPW * PR];                        // payload rings
+    __shared__ uint32_t HST[SPW * HR];                      // header rings
+    __shared__ u32x4 BLK[kEsItemWaves][WSLOT];              // wave-local block records
     __shared__ EsSeg SEG[SPW];
     uint32_t *const PST = reinterpret_cast<uint32_t *>(PST4);
+    uint8_t *const PSTB = reinterpret_cast<uint8_t *>(PST4);
     const uint8_t *const stgb = reinterpret_cast<const uint8_t *>(STG);
 
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -149,17 +160,20 @@ __global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uin
     const Buf out = make_buf(slots + (uint64_t)seg0 * slot_stride, nsw * sstride);
     const uint32_t p0 = (uint32_t)es_p0(g.S >> 3, D, W);
 
+    // the wave's k-th segment and block slot q's segment (in the workgroup)
+    auto wseg = [&](uint32_t k) -> uint32_t { return ((k / SPT) * kEsItemWaves + wave) * SPT + k % SPT; };
+
     // ---- setup ------------------------------------------------------------------
     if (tid < SPW) {
         EsSeg sg;
         const uint32_t nr = tid < nsw ? (uint32_t)min((uint64_t)g.S, g.rows - (uint64_t)(seg0 + tid) * g.S) : 0u;
         sg.nblk = nr >> 3;
         sg.tail = nr & 7u;
-        sg.r = 0; sg.cursor = 0; sg.run = 0; sg.pad0 = 0; sg.pad1 = 0; sg.pad2 = 0;
+        sg.r = 0; sg.cursor = 0; sg.run = 0; sg.r0 = 0; sg.cursor0 = 0; sg.pad = 0;
         SEG[tid] = sg;
     }
-    for (uint32_t k = tid; k < SPW * PSTR; k += G::NT) PST[k] = 0;
-    for (uint32_t k = tid; k < SPW * HSTR; k += G::NT) HST[k] = 0;
+    for (uint32_t k = tid; k < SPW * PR * 4; k += G::NT) PST[k] = 0;
+    for (uint32_t k = tid; k < SPW * HR; k += G::NT) HST[k] = 0;
     if (tid < 64) { PREVX[0][tid] = 0; PREVD[0][tid] = 0; }
 
     // staging of a chunk's rows: 16-byte units over the item lanes
@@ -200,6 +214,12 @@ __global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uin
     auto xval = [&](uint32_t buf, uint32_t s, uint32_t row, uint32_t j) -> uint32_t {
         const uint32_t off = (buf * SPW + s) * SSTR + (row * D + j) * WB;
         return WB == 1 ? (uint32_t)stgb[off] : (uint32_t)*reinterpret_cast<const uint16_t *>(stgb + off);
+    };
+    // a u16 run count at payload byte pos of segment s
+    auto put_count = [&](uint32_t s, uint32_t pos, uint32_t cnt) {
+        uint8_t *const pb = PSTB + s * PR * 16;
+        pb[pos & (PR * 16 - 1)] = (uint8_t)cnt;
+        pb[(pos + 1) & (PR * 16 - 1)] = (uint8_t)(cnt >> 8);
     };
 
     if (!alpha_wave) {
@@ -248,18 +268,19 @@ __global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uin
             if (t >= LAG) {
                 const uint32_t c = t - LAG;
                 const uint32_t buf = c % NBUF;
+                // ---- item lanes: (segment, block, column), every tile of the wave --
+                const uint32_t sl = lane / (CB * DP), b = (lane / DP) % CB, j = lane % DP;
+                const uint32_t bslot = lane / DP;
+                uint32_t z[P][8], width[P], off[P], wsum[P], cwl[P], cwh[P];
+                bool valid[P];
 #pragma unroll
-                for (uint32_t pass = 0; pass < G::PASSES; ++pass) {
-                    const uint32_t tile = pass * kEsItemWaves + wave;
-                    // ---- item lanes: (segment, block, column) ----------------------
-                    const uint32_t sl = lane / (CB * DP), b = (lane / DP) % CB, j = lane % DP;
-                    const uint32_t s = tile * SPT + sl;
+                for (uint32_t pass = 0; pass < P; ++pass) {
+                    const uint32_t s = (pass * kEsItemWaves + wave) * SPT + sl;
                     const uint32_t nblk_s = SEG[s].nblk;
                     const uint32_t bic = c * CB < nblk_s ? min(CB, nblk_s - c * CB) : 0u;
-                    const bool valid = s < nsw && b < bic;
-                    const bool act = valid && j < (uint32_t)D;
+                    valid[pass] = s < nsw && b < bic;
+                    const bool act = valid[pass] && j < (uint32_t)D;
                     const uint32_t ch = s * DP + j;
-                    uint32_t z[8];
                     uint32_t orz = 0;
                     if (act) {
                         uint32_t xp = b == 0 ? PREVX[c & 1][ch] : xval(buf, s, 8 * b - 1, j);
@@ -271,8 +292,8 @@ __global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uin
                             const uint32_t x = xval(buf, s, 8 * b + i, j);
                             const int32_t d = sext<W>((int32_t)(x - xp));
                             const int32_t e = FIRE ? sext<W>(d - (__mul24(alpha, dp) >> W)) : d;
-                            z[i] = zigzag(e);
-                            orz |= z[i];
+                            z[pass][i] = zigzag(e);
+                            orz |= z[pass][i];
                             dp = d;
                             xp = x;
                         }
@@ -282,37 +303,40 @@ __global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uin
                         }
                     } else {
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) z[i] = 0;
+                        for (int i = 0; i < 8; ++i) z[pass][i] = 0;
                     }
                     const uint32_t code = min(bitlen(orz), (uint32_t)W - 1);
-                    const uint32_t width = code < (uint32_t)W - 1 ? code : (uint32_t)W;
-                    const uint32_t wsum = pc_total<DP>(width);
-                    const uint32_t off = pc_incl<DP>(width, j) - width;
+                    width[pass] = code < (uint32_t)W - 1 ? code : (uint32_t)W;
+                    wsum[pass] = pc_total<DP>(width[pass]);
+                    off[pass] = pc_incl<DP>(width[pass], j) - width[pass];
                     // header code word of the block: D fields of HB bits, LSB first
                     const uint32_t cb0 = j * HB;
-                    const uint32_t cw_lo = pc_total<DP>(cb0 < 32 ? code << cb0 : 0u);
-                    uint32_t cw_hi = 0;
+                    cwl[pass] = pc_total<DP>(cb0 < 32 ? code << cb0 : 0u);
+                    cwh[pass] = 0;
                     if constexpr (D * HB > 32)
-                        cw_hi = pc_total<DP>(cb0 + HB <= 32 ? 0u : cb0 >= 32 ? code << (cb0 - 32) : code >> (32 - cb0));
-                    const uint32_t bslot = lane / DP;
+                        cwh[pass] = pc_total<DP>(cb0 + HB <= 32 ? 0u : cb0 >= 32 ? code << (cb0 - 32) : code >> (32 - cb0));
                     if (j == 0) {
                         u32x4 v;
-                        v.x = wsum; v.y = cw_lo; v.z = cw_hi; v.w = valid ? 1u : 0u;
-                        BLK[wave][bslot] = v;
+                        v.x = wsum[pass]; v.y = 0; v.z = 0; v.w = valid[pass] ? 1u : 0u;
+                        BLK[wave][pass * NBS + bslot] = v;
                     }
-                    wave_sync();
-                    // ---- block lanes: (segment, block); records of the chunk ---------
-                    if (lane < NBS) {
-                        const uint32_t bs = lane, bb = bs % CB;
-                        const uint32_t ss = tile * SPT + bs / CB;
-                        const EsSeg q = SEG[ss];
-                        const u32x4 bv = BLK[wave][bs];
+                }
+                wave_sync();
+                // ---- block lanes: (segment, block); records of the chunk -----------
+#pragma unroll
+                for (uint32_t rr = 0; rr < (WSLOT + 63) / 64; ++rr) {
+                    const uint32_t q = lane + 64 * rr;
+                    if (q < WSLOT) {
+                        const uint32_t bb = q % CB;
+                        const uint32_t ss = wseg(q / CB);
+                        const EsSeg sq = SEG[ss];
+                        const u32x4 bv = BLK[wave][q];
                         const bool nz = bv.w != 0 && bv.x != 0;
-                        const uint32_t qbic = c * CB < q.nblk ? min(CB, q.nblk - c * CB) : 0u;
+                        const uint32_t qbic = c * CB < sq.nblk ? min(CB, sq.nblk - c * CB) : 0u;
                         // last nonzero block up to this one, 1-based (0 = none)
                         const uint32_t lastin = es_incl_max<CB>(nz ? bb + 1 : 0u, bb);
                         const uint32_t prevnz = es_prev(lastin, bb);
-                        const uint32_t run = !nz ? 0u : prevnz == 0 ? q.run + bb : bb - prevnz;
+                        const uint32_t run = !nz ? 0u : prevnz == 0 ? sq.run + bb : bb - prevnz;
                         const uint32_t nrle = (run + kRleMax - 1) / kRleMax;
                         const uint32_t psize = COL ? bv.x : 8 * ((bv.x + 7) >> 3);
                         const uint32_t nrec_b = nz ? nrle + 1 : 0u;
@@ -322,122 +346,103 @@ __global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uin
                         const uint32_t nrec_c = pc_total<CB>(nrec_b);
                         const uint32_t pay_c = pc_total<CB>(pay_b);
                         const uint32_t lastall = pc_total<CB>(bb == CB - 1 ? lastin : 0u);
-                        const uint32_t prun = q.cursor + pinc - pay_b;   // its run records
-                        const uint32_t pbase = q.cursor & ~15u;
-                        // run records before the block: u16 counts in the payload staging
-                        uint8_t *const pb = reinterpret_cast<uint8_t *>(PST + ss * PSTR);
-                        for (uint32_t k = 0; k < nrle; ++k) {
-                            const uint32_t cnt = k + 1 < nrle ? kRleMax : run - kRleMax * (nrle - 1);
-                            const uint32_t at = prun + 2 * k - pbase;
-                            pb[at] = (uint8_t)cnt;
-                            pb[at + 1] = (uint8_t)(cnt >> 8);
-                        }
-                        wave_sync();
+                        const uint32_t prun = sq.cursor + pinc - pay_b;   // its run records
+                        for (uint32_t k = 0; k < nrle; ++k)
+                            put_count(ss, prun + 2 * k, k + 1 < nrle ? kRleMax : run - kRleMax * (nrle - 1));
                         u32x4 res;
-                        res.x = q.r + rinc - 1;    // record index of the block
-                        res.y = prun + 2 * nrle;   // payload byte of the block
-                        res.z = q.r;               // records before the chunk
-                        res.w = q.cursor;          // payload bytes before the chunk
-                        BLK[wave][bs] = res;
-                        if (bb == 0 && ss < nsw && qbic > 0) {
+                        res.x = sq.r + rinc - 1;    // record index of the block
+                        res.y = prun + 2 * nrle;    // payload byte of the block
+                        res.z = 0;
+                        res.w = 0;
+                        wave_sync();
+                        BLK[wave][q] = res;
+                        if (bb == 0 && ss < nsw) {
                             EsSeg &ns = SEG[ss];
-                            ns.r = q.r + nrec_c;
-                            ns.cursor = q.cursor + pay_c;
-                            ns.run = lastall == 0 ? q.run + qbic : qbic - lastall;
+                            ns.r0 = sq.r;
+                            ns.cursor0 = sq.cursor;
+                            if (qbic > 0) {
+                                ns.r = sq.r + nrec_c;
+                                ns.cursor = sq.cursor + pay_c;
+                                ns.run = lastall == 0 ? sq.run + qbic : qbic - lastall;
+                            }
                         }
                     } else {
                         wave_sync();
                     }
-                    wave_sync();
-                    // ---- pack: fields and header codes into the staging ---------------
-                    {
-                        const u32x4 res = BLK[wave][bslot];
-                        if (valid && wsum != 0) {
-                            const uint32_t pbase = res.w & ~15u;
-                            uint32_t *const pw = PST + s * PSTR;
-                            const uint32_t pbit = 8 * (res.y - pbase);
-                            const uint32_t rbits = 8 * ((wsum + 7) >> 3);
-                            if (act && width != 0) {
-#pragma unroll
-                                for (int i = 0; i < 8; ++i) {
-                                    const uint32_t p = COL ? pbit + 8 * off + (uint32_t)i * width
-                                                           : pbit + (uint32_t)i * rbits + off;
-                                    const uint32_t sb = p & 31u;
-                                    atomicOr(&pw[p >> 5], z[i] << sb);
-                                    if (sb + width > 32) atomicOr(&pw[(p >> 5) + 1], z[i] >> (32 - sb));
-                                }
-                            }
-                            if (j == 0) {
-                                const uint32_t hb0 = (res.z * D * HB) & ~31u;
-                                const uint32_t lb = res.x * D * HB - hb0;
-                                uint32_t *const hw = HST + s * HSTR + (lb >> 5);
-                                const uint32_t sb = lb & 31u;
-                                if (cw_lo) atomicOr(&hw[0], cw_lo << sb);
-                                if constexpr (D * HB > 32) {
-                                    const uint32_t w1 = (sb ? cw_lo >> (32 - sb) : 0u) | (cw_hi << sb);
-                                    if (w1) atomicOr(&hw[1], w1);
-                                    if (sb && (cw_hi >> (32 - sb))) atomicOr(&hw[2], cw_hi >> (32 - sb));
-                                } else {
-                                    if (sb + D * HB > 32 && (cw_lo >> (32 - sb))) atomicOr(&hw[1], cw_lo >> (32 - sb));
-                                }
-                            }
-                        }
-                    }
-                    wave_sync();
-                    // ---- flush: whole units and header dwords out, the rest stays ------
-                    constexpr uint32_t FP = (SPT * PUNITS + 63) / 64;
-                    constexpr uint32_t FH = (SPT * HSTR + 63) / 64;
-                    u32x4 pcarry[FP];
-                    uint32_t hcarry[FH];
-#pragma unroll
-                    for (uint32_t k = 0; k < FP; ++k) {
-                        const uint32_t f = lane + 64 * k;
-                        const uint32_t fs = f / PUNITS, u = f % PUNITS;
-                        const uint32_t ss = tile * SPT + fs;
-                        pcarry[k] = u32x4{0u, 0u, 0u, 0u};
-                        if (f < SPT * PUNITS && ss < nsw) {
-                            const uint32_t pbase = BLK[wave][fs * CB].w & ~15u;
-                            const uint32_t nfull = (SEG[ss].cursor - pbase) >> 4;
-                            const u32x4 *const pu = PST4 + ss * (PSTR / 4);
-                            if (u < nfull) buf_st128(out, ss * sstride + p0 + pbase + 16 * u, pu[u]);
-                            if (u == 0) pcarry[k] = pu[nfull];
-                        }
-                    }
-#pragma unroll
-                    for (uint32_t k = 0; k < FH; ++k) {
-                        const uint32_t f = lane + 64 * k;
-                        const uint32_t fs = f / HSTR, qd = f % HSTR;
-                        const uint32_t ss = tile * SPT + fs;
-                        hcarry[k] = 0;
-                        if (f < SPT * HSTR && ss < nsw) {
-                            const uint32_t hb0 = (BLK[wave][fs * CB].z * D * HB) & ~31u;
-                            const uint32_t hfull = (SEG[ss].r * D * HB - hb0) >> 5;
-                            const uint32_t *const hw = HST + ss * HSTR;
-                            if (qd < hfull) buf_st32(out, ss * sstride + 4 + hb0 / 8 + 4 * qd, hw[qd]);
-                            if (qd == 0) hcarry[k] = hw[hfull];
-                        }
-                    }
-                    wave_sync();
-#pragma unroll
-                    for (uint32_t k = 0; k < FP; ++k) {
-                        const uint32_t f = lane + 64 * k;
-                        const uint32_t fs = f / PUNITS, u = f % PUNITS;
-                        const uint32_t ss = tile * SPT + fs;
-                        if (f < SPT * PUNITS && ss < nsw) {
-                            const uint32_t pbase = BLK[wave][fs * CB].w & ~15u;
-                            const uint32_t nused = (SEG[ss].cursor - pbase + 15) >> 4;
-                            if (u == 0 || u < nused) PST4[ss * (PSTR / 4) + u] = u == 0 ? pcarry[k] : u32x4{0u, 0u, 0u, 0u};
-                        }
-                    }
-#pragma unroll
-                    for (uint32_t k = 0; k < FH; ++k) {
-                        const uint32_t f = lane + 64 * k;
-                        const uint32_t fs = f / HSTR, qd = f % HSTR;
-                        const uint32_t ss = tile * SPT + fs;
-                        if (f < SPT * HSTR && ss < nsw) HST[ss * HSTR + qd] = qd == 0 ? hcarry[k] : 0u;
-                    }
-                    wave_sync();
                 }
+                wave_sync();
+                // ---- pack: fields and header codes into the rings -------------------
+#pragma unroll
+                for (uint32_t pass = 0; pass < P; ++pass) {
+                    const uint32_t s = (pass * kEsItemWaves + wave) * SPT + sl;
+                    if (valid[pass] && wsum[pass] != 0) {
+                        const u32x4 res = BLK[wave][pass * NBS + bslot];
+                        uint32_t *const pw = PST + s * PR * 4;
+                        const uint32_t pbit = 8 * res.y;
+                        const uint32_t wd = width[pass];
+                        const uint32_t rbits = 8 * ((wsum[pass] + 7) >> 3);
+                        if (j < (uint32_t)D && wd != 0) {
+#pragma unroll
+                            for (int i = 0; i < 8; ++i) {
+                                const uint32_t p = COL ? pbit + 8 * off[pass] + (uint32_t)i * wd
+                                                       : pbit + (uint32_t)i * rbits + off[pass];
+                                const uint32_t sb = p & 31u;
+                                atomicOr(&pw[(p >> 5) & (PR * 4 - 1)], z[pass][i] << sb);
+                                if (sb + wd > 32) atomicOr(&pw[((p >> 5) + 1) & (PR * 4 - 1)], z[pass][i] >> (32 - sb));
+                            }
+                        }
+                        if (j == 0) {
+                            const uint32_t lb = res.x * D * HB;
+                            uint32_t *const hw = HST + s * HR;
+                            const uint32_t q0 = lb >> 5, sb = lb & 31u;
+                            const uint32_t cl = cwl[pass], chh = cwh[pass];
+                            if (cl) atomicOr(&hw[q0 & (HR - 1)], cl << sb);
+                            if constexpr (D * HB > 32) {
+                                const uint32_t w1 = (sb ? cl >> (32 - sb) : 0u) | (chh << sb);
+                                if (w1) atomicOr(&hw[(q0 + 1) & (HR - 1)], w1);
+                                if (sb && (chh >> (32 - sb))) atomicOr(&hw[(q0 + 2) & (HR - 1)], chh >> (32 - sb));
+                            } else {
+                                if (sb + D * HB > 32 && (cl >> (32 - sb))) atomicOr(&hw[(q0 + 1) & (HR - 1)], cl >> (32 - sb));
+                            }
+                        }
+                    }
+                }
+                wave_sync();
+                // ---- flush: units and header dwords completed in this chunk ---------
+                // (each goes out and is cleared in place)
+                constexpr uint32_t FU = (WSEG * G::PUNITS + 63) / 64;
+#pragma unroll
+                for (uint32_t k = 0; k < FU; ++k) {
+                    const uint32_t f = lane + 64 * k;
+                    const uint32_t fs = f / G::PUNITS, u = f % G::PUNITS;
+                    const uint32_t ss = wseg(fs);
+                    if (f < WSEG * G::PUNITS && ss < nsw) {
+                        const EsSeg sq = SEG[ss];
+                        const uint32_t ua = (sq.cursor0 >> 4) + u;
+                        if (ua < (sq.cursor >> 4)) {
+                            u32x4 *const pu = PST4 + ss * PR + (ua & (PR - 1));
+                            buf_st128(out, ss * sstride + p0 + 16 * ua, *pu);
+                            *pu = u32x4{0u, 0u, 0u, 0u};
+                        }
+                    }
+                }
+                constexpr uint32_t FH = (WSEG * G::HSTR + 63) / 64;
+#pragma unroll
+                for (uint32_t k = 0; k < FH; ++k) {
+                    const uint32_t f = lane + 64 * k;
+                    const uint32_t fs = f / G::HSTR, qd = f % G::HSTR;
+                    const uint32_t ss = wseg(fs);
+                    if (f < WSEG * G::HSTR && ss < nsw) {
+                        const EsSeg sq = SEG[ss];
+                        const uint32_t da = ((sq.r0 * D * HB) >> 5) + qd;
+                        if (da < ((sq.r * D * HB) >> 5)) {
+                            uint32_t *const hw = HST + ss * HR + (da & (HR - 1));
+                            buf_st32(out, ss * sstride + 4 + 4 * da, *hw);
+                            *hw = 0;
+                        }
+                    }
+                }
+                wave_sync();
             }
             if (t + 1 < nchunks) stage_commit(t + 1);
         }
@@ -446,47 +451,36 @@ __global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uin
 
     // ---- segment ends: trailing runs, raw tail rows, last units, sizes ----------
     if (!alpha_wave) {
-#pragma unroll
-        for (uint32_t pass = 0; pass < G::PASSES; ++pass) {
-            const uint32_t tile = pass * kEsItemWaves + wave;
-            for (uint32_t fs = 0; fs < SPT; ++fs) {
-                const uint32_t ss = tile * SPT + fs;
-                if (ss >= nsw) break;
-                const EsSeg q = SEG[ss];
-                const uint32_t pbase = q.cursor & ~15u;
-                const uint32_t nrle = (q.run + kRleMax - 1) / kRleMax;
-                uint8_t *const pb = reinterpret_cast<uint8_t *>(PST + ss * PSTR);
-                if (lane < nrle) {
-                    const uint32_t cnt = lane + 1 < nrle ? kRleMax : q.run - kRleMax * (nrle - 1);
-                    const uint32_t at = q.cursor + 2 * lane - pbase;
-                    pb[at] = (uint8_t)cnt;
-                    pb[at + 1] = (uint8_t)(cnt >> 8);
-                }
-                const uint32_t tb = q.tail * D * WB;
-                const uint32_t tpos = q.cursor + 2 * nrle;
-                const uint32_t trow = (ss * g.S + q.nblk * 8) * D * WB;   // in the workgroup's input
-                for (uint32_t k = lane; k < tb; k += 64) pb[tpos - pbase + k] = (uint8_t)buf_ld8(in, trow + k);
-                wave_sync();
-                const uint32_t paytail = tpos + tb;
-                const uint32_t nunits = (paytail - pbase + 15) >> 4;
-                for (uint32_t u = lane; u < nunits; u += 64)
-                    buf_st128(out, ss * sstride + p0 + pbase + 16 * u, PST4[ss * (PSTR / 4) + u]);
-                const uint32_t nrec = q.r + nrle;
-                const uint32_t hbits = nrec * D * HB;
-                const uint32_t hb0 = (q.r * D * HB) & ~31u;
-                const uint32_t ndw = (hbits - hb0 + 31) >> 5;
-                for (uint32_t k = lane; k < ndw; k += 64)
-                    buf_st32(out, ss * sstride + 4 + hb0 / 8 + 4 * k, HST[ss * HSTR + k]);
-                if (lane == 0) {
-                    buf_st32(out, ss * sstride, nrec);
-                    const uint32_t hdr = (hbits + 7) >> 3;
-                    u32x4 v;
-                    v.x = (4 + hdr + paytail + 15) & ~15u;   // segment bytes
-                    v.y = nrec;
-                    v.z = paytail;                           // payload and tail bytes
-                    v.w = 0;
-                    info[seg0 + ss] = v;
-                }
+        for (uint32_t k = 0; k < WSEG; ++k) {
+            const uint32_t ss = wseg(k);
+            if (ss >= nsw) continue;
+            const EsSeg q = SEG[ss];
+            const uint32_t nrle = (q.run + kRleMax - 1) / kRleMax;
+            if (lane < nrle) put_count(ss, q.cursor + 2 * lane, lane + 1 < nrle ? kRleMax : q.run - kRleMax * (nrle - 1));
+            const uint32_t tb = q.tail * D * WB;
+            const uint32_t tpos = q.cursor + 2 * nrle;
+            const uint32_t trow = (ss * g.S + q.nblk * 8) * D * WB;   // in the workgroup's input
+            uint8_t *const pb = PSTB + ss * PR * 16;
+            for (uint32_t i = lane; i < tb; i += 64) pb[(tpos + i) & (PR * 16 - 1)] = (uint8_t)buf_ld8(in, trow + i);
+            wave_sync();
+            const uint32_t paytail = tpos + tb;
+            const uint32_t ufirst = q.cursor >> 4, uend = (paytail + 15) >> 4;
+            for (uint32_t ua = ufirst + lane; ua < uend; ua += 64)
+                buf_st128(out, ss * sstride + p0 + 16 * ua, PST4[ss * PR + (ua & (PR - 1))]);
+            const uint32_t nrec = q.r + nrle;
+            const uint32_t hbits = nrec * D * HB;
+            const uint32_t dfirst = (q.r * D * HB) >> 5, dend = (hbits + 31) >> 5;
+            for (uint32_t da = dfirst + lane; da < dend; da += 64)
+                buf_st32(out, ss * sstride + 4 + 4 * da, HST[ss * HR + (da & (HR - 1))]);
+            if (lane == 0) {
+                buf_st32(out, ss * sstride, nrec);
+                const uint32_t hdr = (hbits + 7) >> 3;
+                u32x4 v;
+                v.x = (4 + hdr + paytail + 15) & ~15u;   // segment bytes
+                v.y = nrec;
+                v.z = paytail;                           // payload and tail bytes
+                v.w = 0;
+                info[seg0 + ss] = v;
             }
         }
     }
