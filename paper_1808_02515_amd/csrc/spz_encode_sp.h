@@ -45,7 +45,10 @@
 
 namespace spz {
 
-constexpr int kEsItemWaves = 4;
+// item waves of a workgroup (eight measured slower: the record scans and
+// flushes then run once per tile instead of once per two tiles)
+__host__ __device__ constexpr uint32_t es_item_waves(uint32_t) { return 4u; }
+__host__ __device__ constexpr uint32_t es_threads(uint32_t D) { return 64 * (es_item_waves(D) + 1); }
 
 // Inclusive max over an aligned group of N <= 16 lanes (values >= 0).
 template <int N> __device__ __forceinline__ uint32_t es_incl_max(uint32_t v, uint32_t i) {
@@ -70,11 +73,18 @@ template <int W, int D> struct EsGeom {
     static constexpr uint32_t CB = DP <= 8 ? 8 : 64 / DP;          // blocks per chunk
     static constexpr uint32_t CR = 8 * CB;                         // rows per chunk
     static constexpr uint32_t SEGB = CR * D * WB;                  // staged bytes of a segment-chunk
-    static constexpr uint32_t SSTR = SEGB + 16;                    // their LDS stride (bank spread)
+    // staged rows carry 16 bytes of padding after every group of GB bytes
+    // (whole blocks, whole 16-byte units), so that the lanes of one row
+    // read, which belong to different blocks, fall into different banks
+    static constexpr uint32_t GB = (8 * D * WB) % 16 == 0 ? 8 * D * WB : 16 * D * WB;
+    static constexpr uint32_t RG = GB / (D * WB);                  // rows per padded group (8 or 16)
+    static constexpr uint32_t SSTR = SEGB + 16 * (SEGB / GB) + 16; // LDS stride of a segment-chunk
     static constexpr uint32_t UNITS = SEGB / 16;                   // 16-byte input units
+    static constexpr uint32_t UG = GB / 16;                        // units per padded group
     static constexpr uint32_t SPT = 64 / (CB * DP);                // segments per wave tile
     static constexpr uint32_t NBS = 64 / DP;                       // block slots per wave tile
-    static constexpr uint32_t PASSES = CB / kEsItemWaves;          // wave tiles per item wave
+    static constexpr uint32_t IW = es_item_waves(D);               // item waves
+    static constexpr uint32_t PASSES = CB / IW;                    // wave tiles per item wave
     static constexpr uint32_t MAXBLK = 8 * D * WB;                 // largest block payload
     // Records in one chunk of one segment: its nonzero blocks, the runs
     // between them, and the pieces of a run carried in from earlier chunks
@@ -88,8 +98,9 @@ template <int W, int D> struct EsGeom {
     static constexpr uint32_t PSTR = PUNITS * 4;                   // dwords
     // header staging: the carried partial dword and one chunk of records
     static constexpr uint32_t HSTR = (32 + MAXREC * D * HB + 31) / 32 + 1;   // dwords
-    static constexpr uint32_t NT = 64 * (kEsItemWaves + 1);
-    static_assert(SEGB % 16 == 0 && CB % kEsItemWaves == 0 && SPT >= 1 && SPT * CB * DP == 64, "geometry");
+    static constexpr uint32_t NT = es_threads(D);
+    static_assert(SEGB % 16 == 0 && CB % IW == 0 && PASSES >= 1 && SPT >= 1 && SPT * CB * DP == 64 &&
+                      (RG == 8 || RG == 16) && SEGB % GB == 0, "geometry");
 };
 
 // Largest header array of a segment with nblk blocks, and the slot layout.
@@ -116,7 +127,7 @@ struct EsSeg {
 __host__ __device__ constexpr uint32_t es_pow2(uint32_t v) { return v <= 1 ? 1u : 2 * es_pow2((v + 1) / 2); }
 
 template <int W, bool FIRE, int D>
-__global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uint8_t *__restrict__ src, Geom g,
+__global__ __launch_bounds__(es_threads(D)) void k_encode_sp(const uint8_t *__restrict__ src, Geom g,
                                                                       uint8_t *__restrict__ slots,
                                                                       uint64_t slot_stride,
                                                                       u32x4 *__restrict__ info) {
@@ -140,14 +151,15 @@ __global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uin
     __shared__ int32_t PREVD[2][64];                        // and its last delta
     __shared__ u32x4 PST4[SPW * PR];                        // payload rings
     __shared__ uint32_t HST[SPW * HR];                      // header rings
-    __shared__ u32x4 BLK[kEsItemWaves][WSLOT];              // wave-local block records
+    __shared__ u32x4 BLK[G::IW][WSLOT];                     // wave-local block records
     __shared__ EsSeg SEG[SPW];
     uint32_t *const PST = reinterpret_cast<uint32_t *>(PST4);
     uint8_t *const PSTB = reinterpret_cast<uint8_t *>(PST4);
     const uint8_t *const stgb = reinterpret_cast<const uint8_t *>(STG);
 
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const bool alpha_wave = wave == kEsItemWaves;
+    constexpr uint32_t IW = G::IW;
+    const bool alpha_wave = wave == IW;
     const uint32_t seg0 = blockIdx.x * SPW;
     const uint32_t nsw = min(SPW, g.nseg - seg0);
 
@@ -161,7 +173,7 @@ __global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uin
     const uint32_t p0 = (uint32_t)es_p0(g.S >> 3, D, W);
 
     // the wave's k-th segment and block slot q's segment (in the workgroup)
-    auto wseg = [&](uint32_t k) -> uint32_t { return ((k / SPT) * kEsItemWaves + wave) * SPT + k % SPT; };
+    auto wseg = [&](uint32_t k) -> uint32_t { return ((k / SPT) * IW + wave) * SPT + k % SPT; };
 
     // ---- setup ------------------------------------------------------------------
     if (tid < SPW) {
@@ -177,7 +189,7 @@ __global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uin
     if (tid < 64) { PREVX[0][tid] = 0; PREVD[0][tid] = 0; }
 
     // staging of a chunk's rows: 16-byte units over the item lanes
-    constexpr uint32_t NIT = 64 * kEsItemWaves;
+    constexpr uint32_t NIT = 64 * IW;
     constexpr uint32_t SUN = (SPW * G::UNITS + NIT - 1) / NIT;
     u32x4 reg[SUN];
     auto stage_issue = [&](uint32_t c) {
@@ -208,11 +220,11 @@ __global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uin
         for (uint32_t t = 0; t < SUN; ++t) {
             const uint32_t u = tid + t * NIT;
             const uint32_t s = u / G::UNITS, k = u % G::UNITS;
-            if (u < SPW * G::UNITS) dstg[s * (SSTR / 16) + k] = reg[t];
+            if (u < SPW * G::UNITS) dstg[s * (SSTR / 16) + k + k / G::UG] = reg[t];
         }
     };
     auto xval = [&](uint32_t buf, uint32_t s, uint32_t row, uint32_t j) -> uint32_t {
-        const uint32_t off = (buf * SPW + s) * SSTR + (row * D + j) * WB;
+        const uint32_t off = (buf * SPW + s) * SSTR + (row * D + j) * WB + 16 * (row / G::RG);
         return WB == 1 ? (uint32_t)stgb[off] : (uint32_t)*reinterpret_cast<const uint16_t *>(stgb + off);
     };
     // a u16 run count at payload byte pos of segment s
@@ -275,7 +287,7 @@ __global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uin
                 bool valid[P];
 #pragma unroll
                 for (uint32_t pass = 0; pass < P; ++pass) {
-                    const uint32_t s = (pass * kEsItemWaves + wave) * SPT + sl;
+                    const uint32_t s = (pass * IW + wave) * SPT + sl;
                     const uint32_t nblk_s = SEG[s].nblk;
                     const uint32_t bic = c * CB < nblk_s ? min(CB, nblk_s - c * CB) : 0u;
                     valid[pass] = s < nsw && b < bic;
@@ -374,7 +386,7 @@ __global__ __launch_bounds__(64 * (kEsItemWaves + 1)) void k_encode_sp(const uin
                 // ---- pack: fields and header codes into the rings -------------------
 #pragma unroll
                 for (uint32_t pass = 0; pass < P; ++pass) {
-                    const uint32_t s = (pass * kEsItemWaves + wave) * SPT + sl;
+                    const uint32_t s = (pass * IW + wave) * SPT + sl;
                     if (valid[pass] && wsum[pass] != 0) {
                         const u32x4 res = BLK[wave][pass * NBS + bslot];
                         uint32_t *const pw = PST + s * PR * 4;
