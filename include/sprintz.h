@@ -66,7 +66,8 @@ typedef enum { SPZ_DELTA = 0, SPZ_FIRE = 1 } spz_forecaster;
 typedef struct {
     uint32_t struct_size;  /* sizeof(spz_params) */
     uint32_t forecaster;   /* spz_forecaster */
-    uint32_t seg_rows;     /* rows per independently coded segment (multiple of 8) */
+    uint32_t seg_rows;     /* rows per independently coded segment (multiple of 8);
+                              0 = autotuned (compression only: see sprintz_autotune) */
     uint32_t hdr_group;    /* records whose headers are stored together (Section 4.3,
                               last paragraph); 0 = one group per segment */
     uint32_t learn_shift;  /* FIRE learning rate eta = 2^-learn_shift (paper: eta = 1/2) */
@@ -127,13 +128,33 @@ spz_status sprintz_compress(const void *d_src, uint64_t rows, uint32_t D, spz_dt
                             const spz_params *p, void *d_dst, size_t dst_cap, uint64_t *d_out_size,
                             void *d_ws, size_t ws_size, int32_t *d_status, hipStream_t stream);
 
+/* The autotuner behind seg_rows = 0. It compresses the first min(rows, 2^20)
+ * rows of d_src at the reference segment size (one segment over them, the
+ * paper's unsegmented stream) and at each candidate 256, 512, 1024, 2048 and
+ * 4096 below it, and times the decoding of each container (best of three,
+ * HIP events). The choice is the fastest decode among the sizes whose
+ * container stays within 1 % of the reference's bytes; if none does, the
+ * smallest container. Only the segment size is searched: waves per segment
+ * and LDS tiles are fixed by the kernels. The result goes to *seg_rows_out
+ * and to a host cache (mutex-protected, keyed by D, w, forecaster,
+ * learn_shift, hdr_group, entropy and the power-of-two size class of the
+ * reference size) that
+ * sprintz_compress with seg_rows = 0 reads; a shape class that is not cached
+ * yet is tuned on the first such call. Synchronous: it allocates scratch
+ * device memory (hipMalloc), waits for `stream` and frees it again.
+ * sprintz_compress_bound and sprintz_workspace_size with seg_rows = 0 hold
+ * for every candidate. */
+spz_status sprintz_autotune(const void *d_src, uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p,
+                            uint32_t *seg_rows_out, hipStream_t stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):
  * sprintz_compress without a workspace argument. The workspace is a static
  * device array of 4 MiB (4,194,304 bytes) inside the library, one per GPU, held until the process ends; its address
  * is looked up once per device on the first call there. The call allocates
  * nothing and otherwise behaves exactly as sprintz_compress (same kernels,
- * same bytes, same argument checks); the single-pass encoder when its
+ * same bytes, same argument checks, except that seg_rows 0 is refused with
+ * SPZ_EINVAL because the autotuner allocates); the single-pass encoder when its
  * workspace fits the array, else the two-pass one. Requests whose
  * sprintz_workspace_size_min exceeds the array (more than 524,287 segments,
  * or entropy = 1 beyond a small shape) return SPZ_ENOSPC before anything is

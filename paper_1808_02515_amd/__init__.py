@@ -63,6 +63,8 @@ _SIGNATURES = {
     "sprintz_compress_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
                                                 ctypes.POINTER(spz_params), ctypes.c_void_p, ctypes.c_size_t,
                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sprintz_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
+                                        ctypes.POINTER(spz_params), ctypes.POINTER(ctypes.c_uint32), ctypes.c_void_p]),
     "sprintz_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(spz_info)]),
     "sprintz_decompress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(spz_info),
                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
@@ -146,6 +148,15 @@ def sprintz_compress_noalloc(d_src: int, rows: int, D: int, dtype: int, p: spz_p
                              d_out_size: int, d_status: int, stream: int) -> int:
     return int(load().sprintz_compress_noalloc(d_src, rows, D, dtype, ctypes.byref(p), d_dst, dst_cap, d_out_size,
                                                d_status, stream))
+
+
+def sprintz_autotune(d_src: int, rows: int, D: int, dtype: int, p: spz_params, stream: int) -> int:
+    """The library's segment-size autotuner (synchronous); returns seg_rows."""
+    out = ctypes.c_uint32(0)
+    rc = int(load().sprintz_autotune(d_src, rows, D, dtype, ctypes.byref(p), ctypes.byref(out), stream))
+    if rc != SPZ_OK:
+        raise SprintzError(rc, "sprintz_autotune")
+    return int(out.value)
 
 
 def sprintz_get_info(h_src: bytes) -> spz_info:

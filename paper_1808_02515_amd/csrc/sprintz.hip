@@ -45,15 +45,31 @@ uint32_t log2_pow2_ceil(uint32_t v) {
 size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-spz_status check_params(const spz_params *p) {
+// seg_rows 0 (autotuned) is accepted where allow_tuned is set: by the
+// compression calls, not in a container
+spz_status check_params(const spz_params *p, bool allow_tuned = false) {
     if (!p || p->struct_size < sizeof(spz_params)) return SPZ_EINVAL;
     if (p->forecaster != SPZ_DELTA && p->forecaster != SPZ_FIRE) return SPZ_EINVAL;
-    if (p->seg_rows < 8 || p->seg_rows % 8 != 0 || p->seg_rows > kMaxSegRows) return SPZ_EINVAL;
+    if (!(allow_tuned && p->seg_rows == 0) && (p->seg_rows < 8 || p->seg_rows % 8 != 0 || p->seg_rows > kMaxSegRows))
+        return SPZ_EINVAL;
     if (p->hdr_group > 255 || p->learn_shift > 8 || p->entropy > 1) return SPZ_EINVAL;
     return SPZ_OK;
 }
 
 uint64_t num_segments(uint64_t rows, uint32_t S) { return rows == 0 ? 0 : (rows + S - 1) / S; }
+
+// Segment sizes the autotuner chooses from for a series of `rows` rows: the
+// reference size (one segment over the first 2^20 rows, the paper's
+// unsegmented stream) and the fixed candidates below it.
+constexpr uint32_t kTuneCands[] = {256, 512, 1024, 2048, 4096};
+std::vector<uint32_t> tune_candidates(uint64_t rows) {
+    const uint64_t r = std::max<uint64_t>(8, std::min<uint64_t>(rows, kMaxSegRows));
+    const uint32_t ref = (uint32_t)((r + 7) & ~7ull);
+    std::vector<uint32_t> c{ref};
+    for (uint32_t S : kTuneCands)
+        if (S < ref) c.push_back(S);
+    return c;
+}
 
 spz::Geom make_geom(uint64_t rows, uint32_t D, uint32_t w, uint32_t S, uint32_t G, uint32_t learn_shift) {
     spz::Geom g;
@@ -257,7 +273,7 @@ static uint64_t plain_segment_max(uint64_t rows, uint32_t D, uint32_t w, const s
 
 static constexpr uint64_t kHufLdsMax = 60 * 1024;   // coded segment image of the entropy write pass
 
-size_t sprintz_compress_bound(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
+static size_t bound_fixed(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
     const uint32_t w = bits_of(dtype);
     if (w == 0 || D == 0 || check_params(p) != SPZ_OK) return 0;
     if (p->entropy == 1) {
@@ -282,13 +298,15 @@ size_t sprintz_compress_bound(uint64_t rows, uint32_t D, spz_dtype dtype, const 
     return total;
 }
 
-size_t sprintz_workspace_size_min(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
+static size_t ws_fixed(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p);
+
+static size_t ws_min_fixed(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
     if (bits_of(dtype) == 0 || D == 0 || check_params(p) != SPZ_OK) return 0;
-    if (p->entropy == 1) return sprintz_workspace_size(rows, D, dtype, p);
+    if (p->entropy == 1) return ws_fixed(rows, D, dtype, p);
     return 8 * (size_t)num_segments(rows, p->seg_rows) + 8;
 }
 
-size_t sprintz_workspace_size(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
+static size_t ws_fixed(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
     if (bits_of(dtype) == 0 || D == 0 || check_params(p) != SPZ_OK) return 0;
     const uint64_t nseg = num_segments(rows, p->seg_rows);
     const uint32_t w = bits_of(dtype);
@@ -298,10 +316,42 @@ size_t sprintz_workspace_size(uint64_t rows, uint32_t D, spz_dtype dtype, const 
         // plain container | its workspace | per-segment code records | plain size
         spz_params pp = *p;
         pp.entropy = 0;
-        return align256(sprintz_compress_bound(rows, D, dtype, &pp)) +
-               align256(sprintz_workspace_size(rows, D, dtype, &pp)) + align256(nseg * spz::kHufInfo) + 256;
+        return align256(bound_fixed(rows, D, dtype, &pp)) +
+               align256(ws_fixed(rows, D, dtype, &pp)) + align256(nseg * spz::kHufInfo) + 256;
     }
     return 8 * (size_t)nseg + 8;
+}
+
+}  // extern "C"
+
+// With seg_rows 0 (autotuned) the sizes hold for every candidate the
+// autotuner can choose.
+template <typename F> static size_t over_candidates(uint64_t rows, const spz_params *p, F f) {
+    if (!p || p->struct_size < sizeof(spz_params)) return 0;
+    if (p->seg_rows != 0) return f(p);
+    size_t m = 0;
+    for (uint32_t S : tune_candidates(rows)) {
+        spz_params q = *p;
+        q.seg_rows = S;
+        const size_t v = f(&q);
+        if (v == 0) return 0;
+        m = std::max(m, v);
+    }
+    return m;
+}
+
+extern "C" {
+
+size_t sprintz_compress_bound(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
+    return over_candidates(rows, p, [&](const spz_params *q) { return bound_fixed(rows, D, dtype, q); });
+}
+
+size_t sprintz_workspace_size(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
+    return over_candidates(rows, p, [&](const spz_params *q) { return ws_fixed(rows, D, dtype, q); });
+}
+
+size_t sprintz_workspace_size_min(uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p) {
+    return over_candidates(rows, p, [&](const spz_params *q) { return ws_min_fixed(rows, D, dtype, q); });
 }
 
 // Entropy-coded compression: the plain container into the workspace, then
@@ -336,13 +386,143 @@ static spz_status compress_entropy(const void *d_src, uint64_t rows, uint32_t D,
     return hipGetLastError() == hipSuccess ? SPZ_OK : SPZ_EHIP;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The autotuner's cache: one segment size per shape class (the first series
+// of a class is measured, later ones reuse its choice).
+struct TuneKey {
+    uint32_t D, w, forecaster, learn_shift, hdr_group, entropy, ref;
+    bool operator<(const TuneKey &o) const {
+        const uint32_t a[7] = {D, w, forecaster, learn_shift, hdr_group, entropy, ref};
+        const uint32_t b[7] = {o.D, o.w, o.forecaster, o.learn_shift, o.hdr_group, o.entropy, o.ref};
+        return std::lexicographical_compare(a, a + 7, b, b + 7);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, uint32_t> g_tune;
+
+// series of one power-of-two size class of their sample share a key
+TuneKey tune_key(uint64_t rows, uint32_t D, uint32_t w, const spz_params *p) {
+    const uint32_t ref = tune_candidates(rows)[0];
+    return TuneKey{D, w, p->forecaster, p->learn_shift, p->hdr_group, p->entropy, 32u - (uint32_t)__builtin_clz(ref)};
+}
+
+// The choice rule: among the candidates whose container is at most 1 % above
+// the reference (cands[0]), the fastest decode; if none qualifies, the
+// smallest container. Ties go to the candidate listed first.
+uint32_t tune_pick(const std::vector<uint32_t> &cands, const std::vector<uint64_t> &bytes,
+                   const std::vector<float> &ms) {
+    int best = -1;
+    for (size_t k = 0; k < cands.size(); ++k)
+        if (bytes[k] * 100 <= bytes[0] * 101 && (best < 0 || ms[k] < ms[best])) best = (int)k;
+    if (best >= 0) return cands[best];
+    size_t small = 0;
+    for (size_t k = 1; k < cands.size(); ++k)
+        if (bytes[k] < bytes[small]) small = k;
+    return cands[small];
+}
+
+}  // namespace
+
+extern "C" {
+
+spz_status sprintz_autotune(const void *d_src, uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p,
+                            uint32_t *seg_rows_out, hipStream_t stream) {
+    const uint32_t w = bits_of(dtype);
+    if (!seg_rows_out || w == 0 || D == 0 || check_params(p, true) != SPZ_OK) return SPZ_EINVAL;
+    if (D > kMaxD) return SPZ_EUNSUPPORTED;
+    if (rows > 0 && !d_src) return SPZ_EINVAL;
+    const std::vector<uint32_t> cands = tune_candidates(rows);
+    const uint64_t n = std::min<uint64_t>(rows, kMaxSegRows);   // the sample: the first 2^20 rows
+    if (cands.size() == 1) {                                    // one segment is the only choice
+        *seg_rows_out = cands[0];
+        return SPZ_OK;
+    }
+    spz_params q = *p;
+    q.seg_rows = 0;
+    const size_t cap = sprintz_compress_bound(n, D, dtype, &q), wsz = sprintz_workspace_size(n, D, dtype, &q);
+    const size_t ybytes = (size_t)(n * D * (w / 8));
+    uint8_t *dst = nullptr, *ws = nullptr, *y = nullptr;
+    uint64_t *small = nullptr;   // [0] container bytes, [1] status words
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    spz_status st = SPZ_OK;
+    std::vector<uint64_t> bytes;
+    std::vector<float> ms;
+    if (hipMalloc(&dst, cap) != hipSuccess || hipMalloc(&ws, wsz) != hipSuccess || hipMalloc(&y, ybytes) != hipSuccess ||
+        hipMalloc(&small, 16) != hipSuccess || hipEventCreate(&ev[0]) != hipSuccess ||
+        hipEventCreate(&ev[1]) != hipSuccess)
+        st = SPZ_ENOMEM;
+    for (size_t k = 0; st == SPZ_OK && k < cands.size(); ++k) {
+        q.seg_rows = cands[k];
+        hipLaunchKernelGGL(spz::k_zero_u32, dim3(1), dim3(64), 0, stream, (uint32_t *)small, 4u);
+        st = sprintz_compress(d_src, n, D, dtype, &q, dst, cap, small, ws, wsz, (int32_t *)(small + 1), stream);
+        uint64_t h[2] = {0, 0};
+        uint8_t head[64];
+        if (st == SPZ_OK && (hipMemcpyAsync(h, small, 16, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                             hipMemcpyAsync(head, dst, 64, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                             hipStreamSynchronize(stream) != hipSuccess))
+            st = SPZ_EHIP;
+        if (st == SPZ_OK && h[1] != 0) st = SPZ_EHIP;
+        spz_info info;
+        if (st == SPZ_OK) st = sprintz_get_info(head, 64, &info);
+        float best = 0;
+        for (int rep = 0; st == SPZ_OK && rep < 4; ++rep) {   // one warm-up, best of three
+            if (hipEventRecord(ev[0], stream) != hipSuccess) st = SPZ_EHIP;
+            if (st == SPZ_OK) st = sprintz_decompress(dst, cap, &info, y, ybytes, nullptr, stream);
+            float t = 0;
+            if (st == SPZ_OK && (hipEventRecord(ev[1], stream) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                                 hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess))
+                st = SPZ_EHIP;
+            if (rep == 1 || (rep > 1 && t < best)) best = t;
+        }
+        bytes.push_back(h[0]);
+        ms.push_back(best);
+    }
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    if (ev[1]) (void)hipEventDestroy(ev[1]);
+    (void)hipFree(dst);
+    (void)hipFree(ws);
+    (void)hipFree(y);
+    (void)hipFree(small);
+    if (st != SPZ_OK) return st;
+    const uint32_t S = tune_pick(cands, bytes, ms);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(rows, D, w, p)] = S;
+    }
+    *seg_rows_out = S;
+    return SPZ_OK;
+}
+
 spz_status sprintz_compress(const void *d_src, uint64_t rows, uint32_t D, spz_dtype dtype, const spz_params *p,
                             void *d_dst, size_t dst_cap, uint64_t *d_out_size, void *d_ws, size_t ws_size,
                             int32_t *d_status, hipStream_t stream) {
     const uint32_t w = bits_of(dtype);
     if (w == 0 || D == 0) return SPZ_EINVAL;
-    spz_status st = check_params(p);
+    spz_status st = check_params(p, true);
     if (st != SPZ_OK) return st;
+    if (p->seg_rows == 0) {
+        // autotuned: the cached choice of this shape class, else measure now
+        if (D > kMaxD) return SPZ_EUNSUPPORTED;
+        if (!d_dst || !d_out_size || (rows > 0 && !d_src) || !d_ws) return SPZ_EINVAL;
+        if (dst_cap < sprintz_compress_bound(rows, D, dtype, p)) return SPZ_ENOSPC;
+        if (ws_size < sprintz_workspace_size_min(rows, D, dtype, p)) return SPZ_ENOSPC;
+        uint32_t S = 0;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune.find(tune_key(rows, D, w, p));
+            if (it != g_tune.end()) S = it->second;
+        }
+        if (S == 0) {
+            st = sprintz_autotune(d_src, rows, D, dtype, p, &S, stream);
+            if (st != SPZ_OK) return st;
+        }
+        spz_params q = *p;
+        q.seg_rows = S;
+        return sprintz_compress(d_src, rows, D, dtype, &q, d_dst, dst_cap, d_out_size, d_ws, ws_size, d_status, stream);
+    }
     if (D > kMaxD) return SPZ_EUNSUPPORTED;
     if (num_segments(rows, p->seg_rows) > 0xFFFFFFFFull) return SPZ_EUNSUPPORTED;
     if (!d_dst || !d_out_size || (rows > 0 && !d_src) || !d_ws) return SPZ_EINVAL;
@@ -391,6 +571,7 @@ spz_status sprintz_compress_noalloc(const void *d_src, uint64_t rows, uint32_t D
     // the same kernels as sprintz_compress, with the library's scratch array
     // as the workspace; every value the kernels read from it is written by
     // the same call first, so nothing needs clearing between calls
+    if (!p || p->seg_rows == 0) return SPZ_EINVAL;   // the autotuner allocates: pass a segment size
     const size_t need = sprintz_workspace_size_min(rows, D, dtype, p);
     if (need > kScratchBytes) return SPZ_ENOSPC;
     void *ws = nullptr;

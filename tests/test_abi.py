@@ -95,7 +95,7 @@ def test_argument_validation_without_gpu(lib):
     assert spz.sprintz_compress(fake, 100, 3, 4, p, fake, 10, fake, fake, 1 << 10, 0, 0) == spz.SPZ_ENOSPC
     assert spz.sprintz_compress(fake, 100, 3, 4, p, fake, 1 << 20, fake, fake, 0, 0, 0) == spz.SPZ_ENOSPC
     assert spz.sprintz_compress(fake, 100, 3, 4, p, fake + 8, 1 << 20, fake, fake, 1 << 10, 0, 0) == spz.SPZ_EINVAL
-    for bad in [spz.make_params("fire", 12), spz.make_params("fire", 0), spz.make_params("fire", 1024, 256),
+    for bad in [spz.make_params("fire", 12), spz.make_params("fire", 4), spz.make_params("fire", 1024, 256),
                 spz.make_params("fire", 1024, 0, 9)]:
         assert spz.sprintz_compress(fake, 100, 3, 4, bad, fake, 1 << 20, fake, fake, 1 << 10, 0, 0) == spz.SPZ_EINVAL
     info = spz.sprintz_get_info(oracle.compress(np.zeros((16, 2), np.int8), "fire", 8)[:64])
@@ -136,3 +136,28 @@ def test_header_sizes_that_wrap_are_rejected(lib):
     info = spz.spz_info.from_buffer_copy(good)
     info.compressed_size = 16
     assert spz.sprintz_decompress(fake, 1 << 20, info, fake, 1 << 20, 0, 0) == spz.SPZ_EINVAL
+
+
+def _tune_candidates(rows):
+    ref = min(1 << 20, (max(rows, 8) + 7) // 8 * 8)
+    return [ref] + [S for S in (256, 512, 1024, 2048, 4096) if S < ref]
+
+
+@pytest.mark.parametrize("dt,code", [(np.int8, 1), (np.uint16, 4)])
+def test_autotuned_sizes_hold_for_every_candidate(lib, dt, code):
+    # seg_rows 0: bound and workspaces are the largest over the segment sizes
+    # the autotuner may choose
+    for rows, D in [(0, 3), (5, 1), (300, 2), (70000, 8), (3_000_000, 4)]:
+        for G in (0, 2):
+            p0 = spz.make_params("fire", 0, G)
+            cands = _tune_candidates(rows)
+            for fn in (spz.sprintz_compress_bound, spz.sprintz_workspace_size, spz.sprintz_workspace_size_min):
+                assert fn(rows, D, code, p0) == max(fn(rows, D, code, spz.make_params("fire", S, G)) for S in cands)
+            assert spz.sprintz_compress_bound(rows, D, code, p0) == max(
+                oracle.compress_bound(rows, D, dt, S, G) for S in cands)
+
+
+def test_noalloc_refuses_autotuned_segments(lib):
+    fake = 1 << 20  # never dereferenced: refused before any HIP call
+    p = spz.make_params("fire", 0)
+    assert spz.sprintz_compress_noalloc(fake, 1000, 2, spz.SPZ_UINT16, p, fake, 1 << 20, fake, 0, 0) == spz.SPZ_EINVAL

@@ -1,0 +1,70 @@
+"""The library's segment-size autotuner (seg_rows = 0, sprintz_autotune):
+the chosen size obeys the documented rule on the oracle's own container
+sizes, and the container equals the oracle's bytes at that size. Calls go
+through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+import paper_1808_02515_amd as spz
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _candidates(rows):
+    # the reference size (one segment over the first 2^20 rows) first, then
+    # the fixed candidates below it
+    ref = min(1 << 20, (max(rows, 8) + 7) // 8 * 8)
+    return [ref] + [S for S in (256, 512, 1024, 2048, 4096) if S < ref]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "no GPU"
+    spz.load()
+    yield
+
+
+CASES = [
+    ("ar2 uint16 D=8", lambda: datagen.ar2_uint16(200003, 8, seed=31), "fire"),
+    ("walk int8 D=1", lambda: datagen.walk_int8(300001, 1, seed=32), "fire"),
+    ("ar2 int16 D=3", lambda: datagen.ar2_uint16(90000, 3, sigma=5, seed=33).astype(np.int16), "delta"),
+    ("uniform uint8 D=2", lambda: datagen.uniform(50000, 2, np.uint8, seed=34), "fire"),
+    ("short", lambda: datagen.ar2_uint16(777, 4, seed=35), "fire"),
+]
+
+
+@pytest.mark.parametrize("name,make,f", CASES, ids=[c[0] for c in CASES])
+def test_autotuned_segment_size_follows_the_rule(name, make, f):
+    x = make()
+    rows = x.shape[0]
+    _say(f"case autotune {name} shape={x.shape} f={f}")
+    c = spz.compress(torch.from_numpy(x).cuda(), f, 0)
+    got = c.cpu().numpy().tobytes()
+    S = int.from_bytes(got[24:28], "little")
+    cands = _candidates(rows)
+    assert S in cands
+    # the rule, on the oracle's container sizes of the tuner's sample
+    sample = x[: min(rows, 1 << 20)]
+    size = {T: len(oracle.compress(sample, f, T)) for T in cands}
+    ok = [T for T in cands if size[T] * 100 <= size[cands[0]] * 101]
+    if ok:
+        assert S in ok, (S, size)
+    else:
+        assert size[S] == min(size.values())
+    assert got == oracle.compress(x, f, S)
+    # the cached choice is what sprintz_autotune reports for the class
+    xd = torch.from_numpy(x).cuda()
+    p = spz.make_params(f, 0)
+    assert spz.sprintz_autotune(xd.data_ptr(), rows, x.shape[1], spz.dtype_code(xd), p,
+                                torch.cuda.current_stream().cuda_stream) in cands
