@@ -250,6 +250,52 @@ spz_status sprintz_batch_decompress(const spz_batch *b, int32_t *d_status, hipSt
 /* Free a plan (NULL is ignored). The caller makes sure no enqueued work uses it. */
 void sprintz_batch_destroy(spz_batch *b);
 
+/* ---- Batched compression --------------------------------------------------
+ *
+ * Compresses many series in one go. Series with hdr_group 0, D <= 16, entropy
+ * 0, 16-byte aligned input and seg_rows * D * w/8 a multiple of 16 are coded
+ * by the single-pass encoder in one persistent grid per class (w,
+ * forecaster, D) that pulls groups of a series' segments from a device queue
+ * (every segment exactly as by sprintz_compress: Algorithm 1 per block), then
+ * one offset scan per series and one compaction launch over all of them; the
+ * other series are compressed one call each inside the same batch call. */
+typedef struct {
+    const void *d_src;     /* (rows, D) row-major input, aligned to the element size */
+    uint64_t rows;
+    uint32_t D;
+    uint32_t dtype;        /* spz_dtype */
+    spz_params params;     /* seg_rows must be set (0 is refused: tune first with sprintz_autotune) */
+    void *d_dst;           /* container, 16-byte aligned */
+    size_t dst_cap;        /* >= sprintz_compress_bound */
+    uint64_t *d_out_size;  /* device word: container bytes, 8-byte aligned */
+} spz_compress_item;
+
+/* Opaque plan of a compression batch. */
+typedef struct spz_cbatch spz_cbatch;
+
+/* Device workspace of a batch: the plan tables and every series' workspace
+ * (0 if an item is invalid). */
+size_t sprintz_compress_batch_workspace_size(const spz_compress_item *items, uint32_t n);
+
+/* Validate n items and build a plan in the caller's workspace d_ws
+ * (256-byte aligned, ws_size >= sprintz_compress_batch_workspace_size): the
+ * tables go up with an asynchronous copy on `stream`; no device memory is
+ * allocated. The first invalid item's status is returned (SPZ_EINVAL,
+ * SPZ_ENOSPC, SPZ_EUNSUPPORTED). The plan keeps the item pointers and its
+ * host copy of the tables until sprintz_compress_batch_destroy. */
+spz_status sprintz_compress_batch_create_in(const spz_compress_item *items, uint32_t n, void *d_ws, size_t ws_size,
+                                            hipStream_t stream, spz_cbatch **out);
+
+/* Enqueue the compression of every item on `stream`. d_status: n int32
+ * device words (zero on entry, or NULL); a size problem of item i sets bit 2
+ * of d_status[i]. Allocates nothing and never synchronizes, so the call can
+ * be captured into a HIP graph. Calls that overlap on one plan race on its
+ * queues and workspace. */
+spz_status sprintz_compress_batch(const spz_cbatch *b, int32_t *d_status, hipStream_t stream);
+
+/* Free a plan (NULL is ignored); its device tables are the caller's memory. */
+void sprintz_compress_batch_destroy(spz_cbatch *b);
+
 /* Static description of a status code. */
 const char *sprintz_strerror(spz_status s);
 

@@ -48,6 +48,12 @@ class spz_batch_item(ctypes.Structure):
                 ("d_dst", ctypes.c_void_p), ("dst_cap", ctypes.c_size_t)]
 
 
+class spz_compress_item(ctypes.Structure):
+    _fields_ = [("d_src", ctypes.c_void_p), ("rows", ctypes.c_uint64), ("D", ctypes.c_uint32),
+                ("dtype", ctypes.c_uint32), ("params", spz_params), ("d_dst", ctypes.c_void_p),
+                ("dst_cap", ctypes.c_size_t), ("d_out_size", ctypes.c_void_p)]
+
+
 _SIGNATURES = {
     "spz_params_default": (None, [ctypes.POINTER(spz_params)]),
     "sprintz_compress_bound": (ctypes.c_size_t, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
@@ -81,6 +87,12 @@ _SIGNATURES = {
                                                ctypes.POINTER(ctypes.c_void_p)]),
     "sprintz_batch_decompress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sprintz_batch_destroy": (None, [ctypes.c_void_p]),
+    "sprintz_compress_batch_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(spz_compress_item), ctypes.c_uint32]),
+    "sprintz_compress_batch_create_in": (ctypes.c_int, [ctypes.POINTER(spz_compress_item), ctypes.c_uint32,
+                                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "sprintz_compress_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sprintz_compress_batch_destroy": (None, [ctypes.c_void_p]),
     "sprintz_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sprintz_format_version": (ctypes.c_int, []),
 }
@@ -220,6 +232,30 @@ def sprintz_batch_decompress(plan: int, d_status: int, stream: int) -> int:
 
 def sprintz_batch_destroy(plan: int) -> None:
     load().sprintz_batch_destroy(plan)
+
+
+def sprintz_compress_batch_workspace_size(items) -> int:
+    n = len(items)
+    arr = (spz_compress_item * max(n, 1))(*items)
+    return int(load().sprintz_compress_batch_workspace_size(arr, n))
+
+
+def sprintz_compress_batch_create_in(items, d_ws: int, ws_size: int, stream: int) -> int:
+    n = len(items)
+    arr = (spz_compress_item * max(n, 1))(*items)
+    h = ctypes.c_void_p()
+    rc = load().sprintz_compress_batch_create_in(arr, n, d_ws, ws_size, stream, ctypes.byref(h))
+    if rc != SPZ_OK:
+        raise SprintzError(rc, "sprintz_compress_batch_create_in")
+    return h.value
+
+
+def sprintz_compress_batch(plan: int, d_status: int, stream: int) -> int:
+    return int(load().sprintz_compress_batch(plan, d_status, stream))
+
+
+def sprintz_compress_batch_destroy(plan: int) -> None:
+    load().sprintz_compress_batch_destroy(plan)
 
 
 def sprintz_strerror(status: int) -> str:
@@ -377,6 +413,66 @@ class BatchDecoder:
     def close(self):
         if getattr(self, "plan", None):
             sprintz_batch_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchEncoder:
+    """A compression plan over many (rows, D) CUDA tensors: one call codes
+    them all (per-class persistent launches over the series' segments, one
+    offset scan per series, one compaction launch). Containers go to
+    ``self.dsts`` (each at its bound); ``sizes()`` returns their byte counts.
+    The plan keeps pointers to the inputs: keep them alive while it is used.
+    seg_rows 0 is resolved here per series with the library's autotuner."""
+
+    def __init__(self, xs, forecaster: str = "fire", seg_rows: int = 1024, learn_shift: int = 1, device="cuda",
+                 stream=None):
+        torch = _torch()
+        self.xs = [x if x.dim() == 2 else x.reshape(-1, 1) for x in xs]
+        sh = _stream_handle(stream)
+        self.params = []
+        for x in self.xs:
+            S = seg_rows
+            if S == 0:
+                S = sprintz_autotune(x.data_ptr(), x.shape[0], x.shape[1], dtype_code(x),
+                                     make_params(forecaster, 0, 0, learn_shift), sh)
+            self.params.append(make_params(forecaster, S, 0, learn_shift))
+        self.dsts = [torch.empty(sprintz_compress_bound(x.shape[0], x.shape[1], dtype_code(x), p), dtype=torch.uint8,
+                                 device=device) for x, p in zip(self.xs, self.params)]
+        self.out_sizes = torch.zeros(max(len(self.xs), 1), dtype=torch.int64, device=device)
+        self.status = torch.zeros(max(len(self.xs), 1), dtype=torch.int32, device=device)
+        items = [spz_compress_item(x.data_ptr(), x.shape[0], x.shape[1], dtype_code(x), p, d.data_ptr(), d.numel(),
+                                   self.out_sizes.data_ptr() + 8 * k)
+                 for k, (x, p, d) in enumerate(zip(self.xs, self.params, self.dsts))]
+        wsz = sprintz_compress_batch_workspace_size(items)
+        if wsz == 0:
+            raise SprintzError(SPZ_EINVAL, "sprintz_compress_batch_workspace_size")
+        self.ws = torch.empty(wsz + 256, dtype=torch.uint8, device=device)
+        base = (self.ws.data_ptr() + 255) & ~255
+        self.plan = sprintz_compress_batch_create_in(items, base, wsz, sh)
+
+    def run(self, stream=None, status=None):
+        """Enqueue the compression of every series (asynchronous)."""
+        st = self.status if status is None else status
+        rc = sprintz_compress_batch(self.plan, st.data_ptr(), _stream_handle(stream))
+        if rc != SPZ_OK:
+            raise SprintzError(rc, "sprintz_compress_batch")
+
+    def containers(self):
+        """The containers as uint8 CUDA tensors of their exact sizes (synchronises)."""
+        torch = _torch()
+        torch.cuda.synchronize()
+        sizes = self.out_sizes.cpu().tolist()
+        return [d[: int(n)] for d, n in zip(self.dsts, sizes)]
+
+    def close(self):
+        if getattr(self, "plan", None):
+            sprintz_compress_batch_destroy(self.plan)
             self.plan = None
 
     def __del__(self):

@@ -964,6 +964,236 @@ void sprintz_batch_destroy(spz_batch *b) {
     delete b;
 }
 
+}  // extern "C"
+
+// ---- Batched compression ------------------------------------------------------
+
+struct spz_cbatch {
+    uint32_t n;
+    std::vector<uint8_t> host;                     // image of the device tables (kept for the upload)
+    spz::EsStream *streams;                        // batched series
+    uint2 *groups[kClasses];                       // per class: (series, first segment)
+    uint32_t ngroups[kClasses], grid[kClasses];
+    uint32_t *queues;
+    uint32_t *scan_list;                           // batched series, one scan workgroup each
+    uint32_t nscan;
+    uint4 *cgroups;                                // compaction groups (series, first segment, count)
+    uint32_t ncgroups;
+    struct Fallback { spz_compress_item item; void *ws; size_t ws_size; uint32_t index; };
+    std::vector<Fallback> fallback;                // series the batched kernels do not take
+};
+
+namespace {
+
+template <int W, bool FIRE, int D>
+uint32_t cbatch_grid_cap() {
+    static std::mutex mu;
+    static std::map<int, uint32_t> cache;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(dev);
+        if (it != cache.end()) return it->second;
+    }
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)spz::k_encode_sp_batch<W, FIRE, D>,
+                                                     spz::es_threads(D), 0) != hipSuccess)
+        return 1;
+    const uint32_t cap = (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)(cus > 0 ? cus : 1);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[dev] = cap;
+    return cap;
+}
+
+spz_status check_compress_item(const spz_compress_item &it) {
+    const spz_dtype dt = (spz_dtype)it.dtype;
+    const uint32_t w = bits_of(dt);
+    if (w == 0 || it.D == 0) return SPZ_EINVAL;
+    spz_status st = check_params(&it.params);   // seg_rows 0 is not taken: tune first
+    if (st != SPZ_OK) return st;
+    if (it.D > kMaxD) return SPZ_EUNSUPPORTED;
+    if (num_segments(it.rows, it.params.seg_rows) > 0xFFFFFFFFull) return SPZ_EUNSUPPORTED;
+    if (!it.d_dst || !it.d_out_size || (it.rows > 0 && !it.d_src)) return SPZ_EINVAL;
+    if (((uintptr_t)it.d_dst & 15) || ((uintptr_t)it.d_src & (w / 8 - 1)) || ((uintptr_t)it.d_out_size & 7))
+        return SPZ_EINVAL;
+    if (it.dst_cap < sprintz_compress_bound(it.rows, it.D, dt, &it.params)) return SPZ_ENOSPC;
+    return SPZ_OK;
+}
+
+bool cbatch_takes(const spz_compress_item &it) {
+    const uint32_t w = bits_of((spz_dtype)it.dtype);
+    return it.params.entropy == 0 && it.params.hdr_group == 0 && it.D >= 1 && it.D <= 16 && it.rows > 0 &&
+           !((uintptr_t)it.d_src & 15) && ((uint64_t)it.params.seg_rows * it.D * (w / 8)) % 16 == 0;
+}
+
+// Builds the plan's tables (b->host) with pointers relative to the device
+// address `base`, and the workspace regions of every series after them;
+// returns the workspace bytes in *total.
+spz_status build_cplan(const spz_compress_item *items, uint32_t n, spz_cbatch *b, uint8_t *base, size_t *total) {
+    b->n = n;
+    std::vector<int> cls(n, -1);
+    uint32_t nb = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const spz_status st = check_compress_item(items[i]);
+        if (st != SPZ_OK) return st;
+        if (cbatch_takes(items[i])) {
+            cls[i] = class_of(bits_of((spz_dtype)items[i].dtype), items[i].params.forecaster == SPZ_FIRE, items[i].D);
+            ++nb;
+        }
+    }
+    std::vector<std::vector<uint2>> grp(kClasses);
+    std::vector<uint4> cg;
+    std::vector<uint32_t> scan;
+    std::vector<uint32_t> sidx(n, ~0u);
+    uint32_t k = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (cls[i] < 0) continue;
+        sidx[i] = k;
+        const uint32_t D = items[i].D, S = items[i].params.seg_rows, w = bits_of((spz_dtype)items[i].dtype);
+        const uint32_t nseg = (uint32_t)num_segments(items[i].rows, S);
+        const uint32_t spw = 64 / spz::pc_pow2(D);
+        for (uint32_t s0 = 0; s0 < nseg; s0 += spw) grp[cls[i]].push_back(make_uint2(k, s0));
+        const uint64_t units = sp_slot_stride(S, D, w) / 16;
+        const uint32_t K = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(256, 2048 / units));
+        for (uint32_t s0 = 0; s0 < nseg; s0 += K) cg.push_back(make_uint4(k, s0, K, 0));
+        scan.push_back(k);
+        ++k;
+    }
+    size_t off = 0;
+    auto carve = [&](size_t sz) { const size_t o = off; off = (off + sz + 255) & ~size_t(255); return o; };
+    const size_t o_streams = carve(sizeof(spz::EsStream) * (size_t)nb);
+    size_t o_grp[kClasses];
+    for (int c = 0; c < kClasses; ++c) o_grp[c] = carve(grp[c].size() * sizeof(uint2));
+    const size_t o_q = carve(sizeof(uint32_t) * kClasses);
+    const size_t o_scan = carve(scan.size() * sizeof(uint32_t));
+    const size_t o_cg = carve(cg.size() * sizeof(uint4));
+    const size_t tables = off;
+    b->host.assign(tables, 0);
+    // per-series workspace regions after the tables
+    spz::EsStream *hs = reinterpret_cast<spz::EsStream *>(b->host.data() + o_streams);
+    b->fallback.clear();
+    for (uint32_t i = 0; i < n; ++i) {
+        const spz_compress_item &it = items[i];
+        const uint32_t w = bits_of((spz_dtype)it.dtype);
+        if (cls[i] < 0) {
+            const size_t wsz = ws_fixed(it.rows, it.D, (spz_dtype)it.dtype, &it.params);
+            const size_t o = carve(std::max<size_t>(wsz, 16));
+            b->fallback.push_back({it, base ? base + o : nullptr, wsz, i});
+            continue;
+        }
+        const uint32_t S = it.params.seg_rows;
+        spz::EsStream &st = hs[sidx[i]];
+        const spz::Geom g = make_geom(it.rows, it.D, w, S, 0, it.params.learn_shift);
+        st.src = (const uint8_t *)it.d_src;
+        st.dst = (uint8_t *)it.d_dst;
+        st.out_size = it.d_out_size;
+        st.rows = it.rows;
+        st.cap = it.dst_cap;
+        st.data_start = g.data_start;
+        st.slot_stride = sp_slot_stride(S, it.D, w);
+        st.D = it.D; st.S = S; st.nseg = g.nseg; st.w = w; st.dtype = it.dtype;
+        st.forecaster = it.params.forecaster; st.learn_shift = it.params.learn_shift; st.sh = g.sh;
+        st.acc_lo = g.acc_lo; st.acc_hi = g.acc_hi;
+        st.status = i; st.pad = 0;
+        const size_t o = carve(sp_workspace_bytes(g.nseg, S, it.D, w));
+        st.info = reinterpret_cast<spz::u32x4 *>(base + o);
+        st.slots = base + o + align256(16 * (size_t)g.nseg);
+    }
+    *total = off;
+    for (int c = 0; c < kClasses; ++c)
+        if (!grp[c].empty()) memcpy(b->host.data() + o_grp[c], grp[c].data(), grp[c].size() * sizeof(uint2));
+    if (!scan.empty()) memcpy(b->host.data() + o_scan, scan.data(), scan.size() * sizeof(uint32_t));
+    if (!cg.empty()) memcpy(b->host.data() + o_cg, cg.data(), cg.size() * sizeof(uint4));
+    b->streams = reinterpret_cast<spz::EsStream *>(base + o_streams);
+    b->queues = reinterpret_cast<uint32_t *>(base + o_q);
+    b->scan_list = reinterpret_cast<uint32_t *>(base + o_scan);
+    b->nscan = (uint32_t)scan.size();
+    b->cgroups = reinterpret_cast<uint4 *>(base + o_cg);
+    b->ncgroups = (uint32_t)cg.size();
+    for (int c = 0; c < kClasses; ++c) {
+        b->groups[c] = reinterpret_cast<uint2 *>(base + o_grp[c]);
+        b->ngroups[c] = (uint32_t)grp[c].size();
+        uint32_t cap = 1;
+        if (b->ngroups[c] && base) {
+#define SPZ_CCAP(W_, F_, D_) if (class_w(c) == W_ && class_fire(c) == F_ && class_D(c) == D_) cap = cbatch_grid_cap<W_, F_, D_>();
+#define SPZ_CCAPD(W_, F_)                                                                                        \
+    SPZ_CCAP(W_, F_, 1) SPZ_CCAP(W_, F_, 2) SPZ_CCAP(W_, F_, 3) SPZ_CCAP(W_, F_, 4) SPZ_CCAP(W_, F_, 5)            \
+    SPZ_CCAP(W_, F_, 6) SPZ_CCAP(W_, F_, 7) SPZ_CCAP(W_, F_, 8) SPZ_CCAP(W_, F_, 9) SPZ_CCAP(W_, F_, 10)           \
+    SPZ_CCAP(W_, F_, 11) SPZ_CCAP(W_, F_, 12) SPZ_CCAP(W_, F_, 13) SPZ_CCAP(W_, F_, 14) SPZ_CCAP(W_, F_, 15)       \
+    SPZ_CCAP(W_, F_, 16)
+            SPZ_CCAPD(8, false) SPZ_CCAPD(8, true) SPZ_CCAPD(16, false) SPZ_CCAPD(16, true)
+#undef SPZ_CCAPD
+#undef SPZ_CCAP
+        }
+        b->grid[c] = std::min(b->ngroups[c], cap);
+    }
+    return SPZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sprintz_compress_batch_workspace_size(const spz_compress_item *items, uint32_t n) {
+    if (n > 0 && !items) return 0;
+    spz_cbatch b{};
+    size_t total = 0;
+    if (build_cplan(items, n, &b, nullptr, &total) != SPZ_OK) return 0;
+    return std::max<size_t>(total, 256);
+}
+
+spz_status sprintz_compress_batch_create_in(const spz_compress_item *items, uint32_t n, void *d_ws, size_t ws_size,
+                                            hipStream_t stream, spz_cbatch **out) {
+    if (!out || (n > 0 && !items) || !d_ws || ((uintptr_t)d_ws & 255)) return SPZ_EINVAL;
+    *out = nullptr;
+    spz_cbatch *b = new (std::nothrow) spz_cbatch();
+    if (!b) return SPZ_ENOMEM;
+    size_t total = 0;
+    spz_status st = build_cplan(items, n, b, (uint8_t *)d_ws, &total);
+    if (st == SPZ_OK && total > ws_size) st = SPZ_ENOSPC;
+    if (st == SPZ_OK && !b->host.empty() &&
+        hipMemcpyAsync(d_ws, b->host.data(), b->host.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
+        st = SPZ_EHIP;
+    if (st != SPZ_OK) { delete b; return st; }
+    *out = b;
+    return SPZ_OK;
+}
+
+spz_status sprintz_compress_batch(const spz_cbatch *b, int32_t *d_status, hipStream_t stream) {
+    if (!b) return SPZ_EINVAL;
+    hipLaunchKernelGGL(spz::k_zero_u32, dim3(1), dim3(64), 0, stream, b->queues, (uint32_t)kClasses);
+    for (int c = 0; c < kClasses; ++c) {
+        if (!b->ngroups[c]) continue;
+#define SPZ_CBL(W_, F_, D_)                                                                                      \
+    if (class_w(c) == W_ && class_fire(c) == F_ && class_D(c) == D_)                                             \
+        hipLaunchKernelGGL((spz::k_encode_sp_batch<W_, F_, D_>), dim3(b->grid[c]), dim3(spz::es_threads(D_)), 0, \
+                           stream, b->streams, b->groups[c], b->ngroups[c], b->queues + c);
+#define SPZ_CBLD(W_, F_)                                                                                  \
+    SPZ_CBL(W_, F_, 1) SPZ_CBL(W_, F_, 2) SPZ_CBL(W_, F_, 3) SPZ_CBL(W_, F_, 4) SPZ_CBL(W_, F_, 5)          \
+    SPZ_CBL(W_, F_, 6) SPZ_CBL(W_, F_, 7) SPZ_CBL(W_, F_, 8) SPZ_CBL(W_, F_, 9) SPZ_CBL(W_, F_, 10)         \
+    SPZ_CBL(W_, F_, 11) SPZ_CBL(W_, F_, 12) SPZ_CBL(W_, F_, 13) SPZ_CBL(W_, F_, 14) SPZ_CBL(W_, F_, 15)     \
+    SPZ_CBL(W_, F_, 16)
+        SPZ_CBLD(8, false) SPZ_CBLD(8, true) SPZ_CBLD(16, false) SPZ_CBLD(16, true)
+#undef SPZ_CBLD
+#undef SPZ_CBL
+    }
+    if (b->nscan) hipLaunchKernelGGL(spz::k_enc_scan_batch, dim3(b->nscan), dim3(256), 0, stream, b->streams,
+                                     b->scan_list, d_status);
+    if (b->ncgroups) hipLaunchKernelGGL(spz::k_enc_compact_batch, dim3(b->ncgroups), dim3(256), 0, stream, b->streams,
+                                        b->cgroups, d_status);
+    for (const spz_cbatch::Fallback &f : b->fallback) {
+        const spz_compress_item &it = f.item;
+        const spz_status st = sprintz_compress(it.d_src, it.rows, it.D, (spz_dtype)it.dtype, &it.params, it.d_dst,
+                                               it.dst_cap, it.d_out_size, f.ws, f.ws_size,
+                                               d_status ? d_status + f.index : nullptr, stream);
+        if (st != SPZ_OK) return st;
+    }
+    return hipGetLastError() == hipSuccess ? SPZ_OK : SPZ_EHIP;
+}
+
+void sprintz_compress_batch_destroy(spz_cbatch *b) { delete b; }
+
 const char *sprintz_strerror(spz_status s) {
     switch (s) {
         case SPZ_OK: return "ok";

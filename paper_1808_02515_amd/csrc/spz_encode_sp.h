@@ -126,11 +126,17 @@ struct EsSeg {
 
 __host__ __device__ constexpr uint32_t es_pow2(uint32_t v) { return v <= 1 ? 1u : 2 * es_pow2((v + 1) / 2); }
 
-template <int W, bool FIRE, int D>
-__global__ __launch_bounds__(es_threads(D)) void k_encode_sp(const uint8_t *__restrict__ src, Geom g,
-                                                                      uint8_t *__restrict__ slots,
-                                                                      uint64_t slot_stride,
-                                                                      u32x4 *__restrict__ info) {
+// One workgroup's job: up to SPW consecutive segments of one series.
+struct EsJob {
+    const uint8_t *src;   // the series' rows
+    uint8_t *slots;       // its workspace slots (slot_stride bytes each)
+    u32x4 *info;          // its segment info records
+    uint64_t rows, slot_stride;
+    uint32_t S, nseg, seg0, sh;
+    int32_t acc_lo, acc_hi;
+};
+
+template <int W, bool FIRE, int D> __device__ __forceinline__ void es_encode_group(const EsJob &jb) {
     using G = EsGeom<W, D>;
     constexpr uint32_t HB = G::HB, WB = G::WB, DP = G::DP, SPW = G::SPW, CB = G::CB, CR = G::CR;
     constexpr uint32_t SSTR = G::SSTR, SPT = G::SPT, NBS = G::NBS, P = G::PASSES;
@@ -160,17 +166,21 @@ __global__ __launch_bounds__(es_threads(D)) void k_encode_sp(const uint8_t *__re
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     constexpr uint32_t IW = G::IW;
     const bool alpha_wave = wave == IW;
-    const uint32_t seg0 = blockIdx.x * SPW;
-    const uint32_t nsw = min(SPW, g.nseg - seg0);
+    const uint32_t seg0 = jb.seg0;
+    const uint8_t *const src = jb.src;
+    uint8_t *const slots = jb.slots;
+    u32x4 *const info = jb.info;
+    const uint64_t slot_stride = jb.slot_stride;
+    const uint32_t nsw = min(SPW, jb.nseg - seg0);
 
     // bounded views: this workgroup's input rows and its workspace slots
-    const uint64_t wrow0 = (uint64_t)seg0 * g.S;
-    const uint64_t wrows = min((uint64_t)nsw * g.S, g.rows - wrow0);
+    const uint64_t wrow0 = (uint64_t)seg0 * jb.S;
+    const uint64_t wrows = min((uint64_t)nsw * jb.S, jb.rows - wrow0);
     const uint32_t in_bytes = (uint32_t)(wrows * D * WB);
     const Buf in = make_buf(src + wrow0 * D * WB, in_bytes);
     const uint32_t sstride = (uint32_t)slot_stride;
     const Buf out = make_buf(slots + (uint64_t)seg0 * slot_stride, nsw * sstride);
-    const uint32_t p0 = (uint32_t)es_p0(g.S >> 3, D, W);
+    const uint32_t p0 = (uint32_t)es_p0(jb.S >> 3, D, W);
 
     // the wave's k-th segment and block slot q's segment (in the workgroup)
     auto wseg = [&](uint32_t k) -> uint32_t { return ((k / SPT) * IW + wave) * SPT + k % SPT; };
@@ -178,7 +188,7 @@ __global__ __launch_bounds__(es_threads(D)) void k_encode_sp(const uint8_t *__re
     // ---- setup ------------------------------------------------------------------
     if (tid < SPW) {
         EsSeg sg;
-        const uint32_t nr = tid < nsw ? (uint32_t)min((uint64_t)g.S, g.rows - (uint64_t)(seg0 + tid) * g.S) : 0u;
+        const uint32_t nr = tid < nsw ? (uint32_t)min((uint64_t)jb.S, jb.rows - (uint64_t)(seg0 + tid) * jb.S) : 0u;
         sg.nblk = nr >> 3;
         sg.tail = nr & 7u;
         sg.r = 0; sg.cursor = 0; sg.run = 0; sg.r0 = 0; sg.cursor0 = 0; sg.pad = 0;
@@ -199,7 +209,7 @@ __global__ __launch_bounds__(es_threads(D)) void k_encode_sp(const uint8_t *__re
             const uint32_t s = u / G::UNITS, k = u % G::UNITS;
             u32x4 v = {0u, 0u, 0u, 0u};
             if (u < SPW * G::UNITS && s < nsw) {
-                const uint32_t off = (s * g.S + c * CR) * D * WB + 16 * k;
+                const uint32_t off = (s * jb.S + c * CR) * D * WB + 16 * k;
                 if (off + 16 <= in_bytes) {
                     v = buf_ld128(in, off);
                 } else if (off < in_bytes) {
@@ -240,7 +250,7 @@ __global__ __launch_bounds__(es_threads(D)) void k_encode_sp(const uint8_t *__re
     }
     __syncthreads();
 
-    const uint32_t nchunks = ((g.S >> 3) + CB - 1) / CB;
+    const uint32_t nchunks = ((jb.S >> 3) + CB - 1) / CB;
 
     // alpha wave state: one column chain per lane
     const uint32_t a_s = lane / DP, a_j = lane % DP;
@@ -259,7 +269,7 @@ __global__ __launch_bounds__(es_threads(D)) void k_encode_sp(const uint8_t *__re
                     uint32_t xs[8];
 #pragma unroll
                     for (int i = 0; i < 8; ++i) xs[i] = xval(buf, a_s, 8 * b + i, a_j);
-                    const int32_t alpha = acc >> g.sh;
+                    const int32_t alpha = acc >> jb.sh;
                     ALPHA[((t & 1) * 64 + lane) * CB + b] = alpha;
                     int32_t grad = 0;
 #pragma unroll
@@ -272,7 +282,7 @@ __global__ __launch_bounds__(es_threads(D)) void k_encode_sp(const uint8_t *__re
                         a_d = d;
                         a_x = xs[i];
                     }
-                    acc = min(max(acc + grad, g.acc_lo), g.acc_hi);
+                    acc = min(max(acc + grad, jb.acc_lo), jb.acc_hi);
                 }
             }
         } else {
@@ -471,7 +481,7 @@ __global__ __launch_bounds__(es_threads(D)) void k_encode_sp(const uint8_t *__re
             if (lane < nrle) put_count(ss, q.cursor + 2 * lane, lane + 1 < nrle ? kRleMax : q.run - kRleMax * (nrle - 1));
             const uint32_t tb = q.tail * D * WB;
             const uint32_t tpos = q.cursor + 2 * nrle;
-            const uint32_t trow = (ss * g.S + q.nblk * 8) * D * WB;   // in the workgroup's input
+            const uint32_t trow = (ss * jb.S + q.nblk * 8) * D * WB;   // in the workgroup's input
             uint8_t *const pb = PSTB + ss * PR * 16;
             for (uint32_t i = lane; i < tb; i += 64) pb[(tpos + i) & (PR * 16 - 1)] = (uint8_t)buf_ld8(in, trow + i);
             wave_sync();
@@ -498,16 +508,61 @@ __global__ __launch_bounds__(es_threads(D)) void k_encode_sp(const uint8_t *__re
     }
 }
 
+template <int W, bool FIRE, int D>
+__global__ __launch_bounds__(es_threads(D)) void k_encode_sp(const uint8_t *__restrict__ src, Geom g,
+                                                              uint8_t *__restrict__ slots, uint64_t slot_stride,
+                                                              u32x4 *__restrict__ info) {
+    const EsJob jb{src, slots, info, g.rows, slot_stride, g.S, g.nseg, blockIdx.x * EsGeom<W, D>::SPW, g.sh,
+                   g.acc_lo, g.acc_hi};
+    es_encode_group<W, FIRE, D>(jb);
+}
+
+// One series of a compression batch, as the batched kernels see it.
+struct EsStream {
+    const uint8_t *src;
+    uint8_t *dst;         // container
+    uint8_t *slots;
+    u32x4 *info;
+    uint64_t *out_size;
+    uint64_t rows, cap, data_start, slot_stride;
+    uint32_t D, S, nseg, w, dtype, forecaster, learn_shift, sh;
+    int32_t acc_lo, acc_hi;
+    uint32_t status, pad;   // index of the series' status word
+};
+
+// Many series of one class (w, forecaster, D): a persistent grid pulls
+// groups (series, first segment) from a device queue.
+template <int W, bool FIRE, int D>
+__global__ __launch_bounds__(es_threads(D)) void k_encode_sp_batch(const EsStream *__restrict__ streams,
+                                                                    const uint2 *__restrict__ groups, uint32_t ngroups,
+                                                                    uint32_t *__restrict__ queue) {
+    __shared__ uint32_t grp_sh;
+    for (;;) {
+        if (threadIdx.x == 0) grp_sh = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t grp = grp_sh;
+        __syncthreads();
+        if (grp >= ngroups) break;
+        const uint2 gr = groups[grp];
+        const EsStream &st = streams[gr.x];
+        const EsJob jb{st.src, st.slots, st.info, st.rows, st.slot_stride, st.S, st.nseg, gr.y, st.sh, st.acc_lo,
+                       st.acc_hi};
+        es_encode_group<W, FIRE, D>(jb);
+        __syncthreads();
+    }
+}
+
 // Offset table and container header from the segment sizes (one workgroup):
 // each thread sums a contiguous run of segments, one block scan, then the
 // table entries of its run.
-__global__ __launch_bounds__(1024) void k_enc_scan(const u32x4 *__restrict__ info, Geom g, uint32_t w, uint32_t dtype,
-                                                   uint32_t forecaster, uint32_t learn_shift, uint8_t *__restrict__ dst,
-                                                   uint64_t *__restrict__ out_size, int32_t *__restrict__ status) {
+__device__ __forceinline__ void es_scan_body(const u32x4 *__restrict__ info, uint32_t n, uint64_t rows, uint32_t D,
+                                             uint32_t S, uint32_t G, uint64_t data_start, uint64_t cap, uint32_t w,
+                                             uint32_t dtype, uint32_t forecaster, uint32_t learn_shift,
+                                             uint8_t *__restrict__ dst, uint64_t *__restrict__ out_size,
+                                             int32_t *__restrict__ status) {
     __shared__ uint64_t wsum[16];
-    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const uint32_t n = g.nseg;
-    const uint32_t per = (n + 1023) / 1024;
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6, nt = blockDim.x, nw = nt >> 6;
+    const uint32_t per = (n + nt - 1) / nt;
     const uint32_t k0 = min(n, t * per), k1 = min(n, k0 + per);
     uint64_t mine = 0;
     for (uint32_t k = k0; k < k1; ++k) mine += info[k].x;
@@ -519,7 +574,7 @@ __global__ __launch_bounds__(1024) void k_enc_scan(const u32x4 *__restrict__ inf
     if (lane == 63) wsum[wv] = incl;
     __syncthreads();
     uint64_t before = 0, total = 0;
-    for (uint32_t q = 0; q < 16; ++q) {
+    for (uint32_t q = 0; q < nw; ++q) {
         const uint64_t v = wsum[q];
         if (q < wv) before += v;
         total += v;
@@ -537,11 +592,11 @@ __global__ __launch_bounds__(1024) void k_enc_scan(const u32x4 *__restrict__ inf
         switch (t) {
             case 0: word = 0x315A5053u; break;                                            // "SPZ1"
             case 1: word = 1u | (w << 16) | (dtype << 24); break;                          // version, w, dtype
-            case 2: word = forecaster | (learn_shift << 8) | (g.G << 16); break;           // entropy 0
-            case 3: word = g.D; break;
-            case 4: word = (uint32_t)g.rows; break;
-            case 5: word = (uint32_t)(g.rows >> 32); break;
-            case 6: word = g.S; break;
+            case 2: word = forecaster | (learn_shift << 8) | (G << 16); break;             // entropy 0
+            case 3: word = D; break;
+            case 4: word = (uint32_t)rows; break;
+            case 5: word = (uint32_t)(rows >> 32); break;
+            case 6: word = S; break;
             case 7: word = n; break;
             case 8: word = (uint32_t)total; break;
             case 9: word = (uint32_t)(total >> 32); break;
@@ -551,36 +606,50 @@ __global__ __launch_bounds__(1024) void k_enc_scan(const u32x4 *__restrict__ inf
     }
     // zero padding between the offset table and the data
     const uint64_t pad0 = 64 + 8ull * (n + 1);
-    if (t < g.data_start - pad0) dst[pad0 + t] = 0;
+    if (t < data_start - pad0) dst[pad0 + t] = 0;
     if (t == 0) {
-        *out_size = g.data_start + total;
-        if (g.data_start + total > g.cap && status) atomicOr(status, 2);
+        *out_size = data_start + total;
+        if (data_start + total > cap && status) atomicOr(status, 2);
     }
+}
+
+__global__ __launch_bounds__(1024) void k_enc_scan(const u32x4 *__restrict__ info, Geom g, uint32_t w, uint32_t dtype,
+                                                   uint32_t forecaster, uint32_t learn_shift, uint8_t *__restrict__ dst,
+                                                   uint64_t *__restrict__ out_size, int32_t *__restrict__ status) {
+    es_scan_body(info, g.nseg, g.rows, g.D, g.S, g.G, g.data_start, g.cap, w, dtype, forecaster, learn_shift, dst,
+                 out_size, status);
+}
+
+// One workgroup per series of a compression batch.
+__global__ __launch_bounds__(256) void k_enc_scan_batch(const EsStream *__restrict__ streams, const uint32_t *__restrict__ list,
+                                                        int32_t *__restrict__ status) {
+    const EsStream &st = streams[list[blockIdx.x]];
+    es_scan_body(st.info, st.nseg, st.rows, st.D, st.S, 0, st.data_start, st.cap, st.w, st.dtype, st.forecaster,
+                 st.learn_shift, st.dst, st.out_size, status ? status + st.status : nullptr);
 }
 
 // Copies K segments per workgroup from their workspace slots to the
 // container: destination units of 16 bytes, bytes [0, 4 + header) from the
 // slot's start and the rest from its payload at P0, zero padding at the end.
-__global__ __launch_bounds__(256) void k_enc_compact(const uint8_t *__restrict__ slots, uint64_t slot_stride,
-                                                     const u32x4 *__restrict__ info, Geom g, uint32_t w,
-                                                     uint32_t K, uint8_t *__restrict__ dst,
-                                                     int32_t *__restrict__ status) {
-    const uint32_t first = blockIdx.x * K;
-    if (first >= g.nseg) return;
-    const uint32_t last = min(g.nseg, first + K);
+__device__ __forceinline__ void es_compact_body(const uint8_t *__restrict__ slots, uint64_t slot_stride,
+                                                const u32x4 *__restrict__ info, uint32_t nseg, uint64_t data_start,
+                                                uint64_t cap, uint32_t D, uint32_t S, uint32_t w, uint32_t first,
+                                                uint32_t K, uint8_t *__restrict__ dst, int32_t *__restrict__ status) {
+    if (first >= nseg) return;
+    const uint32_t last = min(nseg, first + K);
     const uint64_t *tab = reinterpret_cast<const uint64_t *>(dst + 64);
     const uint64_t o0 = tab[first], o1 = tab[last];
-    if (g.data_start + o1 > g.cap || o1 < o0 || o1 - o0 > 0xFFFFFFF0ull) {
+    if (data_start + o1 > cap || o1 < o0 || o1 - o0 > 0xFFFFFFF0ull) {
         if (threadIdx.x == 0 && status) atomicOr(status, 2);
         return;
     }
     const Buf sb = make_buf(slots + (uint64_t)first * slot_stride, (uint32_t)((last - first) * slot_stride));
-    const Buf db = make_buf(dst + g.data_start + o0, (uint32_t)(o1 - o0));
+    const Buf db = make_buf(dst + data_start + o0, (uint32_t)(o1 - o0));
     const uint32_t hb = w == 8 ? 3u : 4u;
-    const uint32_t p0 = (uint32_t)es_p0(g.S >> 3, g.D, w);
+    const uint32_t p0 = (uint32_t)es_p0(S >> 3, D, w);
     for (uint32_t s = first; s < last; ++s) {
         const u32x4 in = info[s];
-        const uint32_t size = in.x, A = 4 + (uint32_t)(((uint64_t)in.y * g.D * hb + 7) >> 3), PT = in.z;
+        const uint32_t size = in.x, A = 4 + (uint32_t)(((uint64_t)in.y * D * hb + 7) >> 3), PT = in.z;
         const uint32_t sbase = (s - first) * (uint32_t)slot_stride;
         const uint32_t dbase = (uint32_t)(tab[s] - o0);
         if (size % 16 || size > slot_stride || A + PT > size || tab[s + 1] - tab[s] != size) {
@@ -619,6 +688,22 @@ __global__ __launch_bounds__(256) void k_enc_compact(const uint8_t *__restrict__
             buf_st128(db, dbase + k0, o);
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_enc_compact(const uint8_t *__restrict__ slots, uint64_t slot_stride,
+                                                     const u32x4 *__restrict__ info, Geom g, uint32_t w, uint32_t K,
+                                                     uint8_t *__restrict__ dst, int32_t *__restrict__ status) {
+    es_compact_body(slots, slot_stride, info, g.nseg, g.data_start, g.cap, g.D, g.S, w, blockIdx.x * K, K, dst, status);
+}
+
+// Compaction groups of a compression batch: (series, first segment, count).
+__global__ __launch_bounds__(256) void k_enc_compact_batch(const EsStream *__restrict__ streams,
+                                                           const uint4 *__restrict__ groups,
+                                                           int32_t *__restrict__ status) {
+    const uint4 gr = groups[blockIdx.x];
+    const EsStream &st = streams[gr.x];
+    es_compact_body(st.slots, st.slot_stride, st.info, st.nseg, st.data_start, st.cap, st.D, st.S, st.w, gr.y, gr.z,
+                    st.dst, status ? status + st.status : nullptr);
 }
 
 }  // namespace spz
