@@ -253,7 +253,8 @@ void sprintz_batch_destroy(spz_batch *b);
 /* ---- Batched compression --------------------------------------------------
  *
  * Compresses many series in one go. Series with hdr_group 0, D <= 16, entropy
- * 0, 16-byte aligned input and seg_rows * D * w/8 a multiple of 16 are coded
+ * 0, 16-byte aligned input, seg_rows * D * w/8 a multiple of 16 and a
+ * workspace of at least sprintz_workspace_size bytes are coded
  * by the single-pass encoder in one persistent grid per class (w,
  * forecaster, D) that pulls groups of a series' segments from a device queue
  * (every segment exactly as by sprintz_compress: Algorithm 1 per block), then
@@ -268,13 +269,15 @@ typedef struct {
     void *d_dst;           /* container, 16-byte aligned */
     size_t dst_cap;        /* >= sprintz_compress_bound */
     uint64_t *d_out_size;  /* device word: container bytes, 8-byte aligned */
+    void *d_ws;            /* the series' workspace, 16-byte aligned; the batched encoder takes it when */
+    size_t ws_size;        /* ws_size >= sprintz_workspace_size, else the series takes one call (>= the minimum) */
 } spz_compress_item;
 
 /* Opaque plan of a compression batch. */
 typedef struct spz_cbatch spz_cbatch;
 
-/* Device workspace of a batch: the plan tables and every series' workspace
- * (0 if an item is invalid). */
+/* Device bytes of a batch's plan tables (0 if an item is invalid); every
+ * series brings its own workspace in its item. */
 size_t sprintz_compress_batch_workspace_size(const spz_compress_item *items, uint32_t n);
 
 /* Validate n items and build a plan in the caller's workspace d_ws

@@ -51,7 +51,8 @@ class spz_batch_item(ctypes.Structure):
 class spz_compress_item(ctypes.Structure):
     _fields_ = [("d_src", ctypes.c_void_p), ("rows", ctypes.c_uint64), ("D", ctypes.c_uint32),
                 ("dtype", ctypes.c_uint32), ("params", spz_params), ("d_dst", ctypes.c_void_p),
-                ("dst_cap", ctypes.c_size_t), ("d_out_size", ctypes.c_void_p)]
+                ("dst_cap", ctypes.c_size_t), ("d_out_size", ctypes.c_void_p), ("d_ws", ctypes.c_void_p),
+                ("ws_size", ctypes.c_size_t)]
 
 
 _SIGNATURES = {
@@ -446,9 +447,11 @@ class BatchEncoder:
                                  device=device) for x, p in zip(self.xs, self.params)]
         self.out_sizes = torch.zeros(max(len(self.xs), 1), dtype=torch.int64, device=device)
         self.status = torch.zeros(max(len(self.xs), 1), dtype=torch.int32, device=device)
+        self.wss = [torch.empty(max(sprintz_workspace_size(x.shape[0], x.shape[1], dtype_code(x), p), 16),
+                                dtype=torch.uint8, device=device) for x, p in zip(self.xs, self.params)]
         items = [spz_compress_item(x.data_ptr(), x.shape[0], x.shape[1], dtype_code(x), p, d.data_ptr(), d.numel(),
-                                   self.out_sizes.data_ptr() + 8 * k)
-                 for k, (x, p, d) in enumerate(zip(self.xs, self.params, self.dsts))]
+                                   self.out_sizes.data_ptr() + 8 * k, w.data_ptr(), w.numel())
+                 for k, (x, p, d, w) in enumerate(zip(self.xs, self.params, self.dsts, self.wss))]
         wsz = sprintz_compress_batch_workspace_size(items)
         if wsz == 0:
             raise SprintzError(SPZ_EINVAL, "sprintz_compress_batch_workspace_size")

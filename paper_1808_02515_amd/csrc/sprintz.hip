@@ -1018,18 +1018,21 @@ spz_status check_compress_item(const spz_compress_item &it) {
     if (((uintptr_t)it.d_dst & 15) || ((uintptr_t)it.d_src & (w / 8 - 1)) || ((uintptr_t)it.d_out_size & 7))
         return SPZ_EINVAL;
     if (it.dst_cap < sprintz_compress_bound(it.rows, it.D, dt, &it.params)) return SPZ_ENOSPC;
+    if (!it.d_ws || ((uintptr_t)it.d_ws & 15)) return SPZ_EINVAL;
+    if (it.ws_size < sprintz_workspace_size_min(it.rows, it.D, dt, &it.params)) return SPZ_ENOSPC;
     return SPZ_OK;
 }
 
 bool cbatch_takes(const spz_compress_item &it) {
     const uint32_t w = bits_of((spz_dtype)it.dtype);
     return it.params.entropy == 0 && it.params.hdr_group == 0 && it.D >= 1 && it.D <= 16 && it.rows > 0 &&
-           !((uintptr_t)it.d_src & 15) && ((uint64_t)it.params.seg_rows * it.D * (w / 8)) % 16 == 0;
+           !((uintptr_t)it.d_src & 15) && ((uint64_t)it.params.seg_rows * it.D * (w / 8)) % 16 == 0 &&
+           it.ws_size >= sp_workspace_bytes(num_segments(it.rows, it.params.seg_rows), it.params.seg_rows, it.D, w);
 }
 
 // Builds the plan's tables (b->host) with pointers relative to the device
-// address `base`, and the workspace regions of every series after them;
-// returns the workspace bytes in *total.
+// address `base`; returns their bytes in *total. Every series codes into its
+// own workspace.
 spz_status build_cplan(const spz_compress_item *items, uint32_t n, spz_cbatch *b, uint8_t *base, size_t *total) {
     b->n = n;
     std::vector<int> cls(n, -1);
@@ -1068,8 +1071,7 @@ spz_status build_cplan(const spz_compress_item *items, uint32_t n, spz_cbatch *b
     const size_t o_q = carve(sizeof(uint32_t) * kClasses);
     const size_t o_scan = carve(scan.size() * sizeof(uint32_t));
     const size_t o_cg = carve(cg.size() * sizeof(uint4));
-    const size_t tables = off;
-    b->host.assign(tables, 0);
+    b->host.assign(off, 0);
     // per-series workspace regions after the tables
     spz::EsStream *hs = reinterpret_cast<spz::EsStream *>(b->host.data() + o_streams);
     b->fallback.clear();
@@ -1077,9 +1079,7 @@ spz_status build_cplan(const spz_compress_item *items, uint32_t n, spz_cbatch *b
         const spz_compress_item &it = items[i];
         const uint32_t w = bits_of((spz_dtype)it.dtype);
         if (cls[i] < 0) {
-            const size_t wsz = ws_fixed(it.rows, it.D, (spz_dtype)it.dtype, &it.params);
-            const size_t o = carve(std::max<size_t>(wsz, 16));
-            b->fallback.push_back({it, base ? base + o : nullptr, wsz, i});
+            b->fallback.push_back({it, it.d_ws, it.ws_size, i});
             continue;
         }
         const uint32_t S = it.params.seg_rows;
@@ -1096,9 +1096,8 @@ spz_status build_cplan(const spz_compress_item *items, uint32_t n, spz_cbatch *b
         st.forecaster = it.params.forecaster; st.learn_shift = it.params.learn_shift; st.sh = g.sh;
         st.acc_lo = g.acc_lo; st.acc_hi = g.acc_hi;
         st.status = i; st.pad = 0;
-        const size_t o = carve(sp_workspace_bytes(g.nseg, S, it.D, w));
-        st.info = reinterpret_cast<spz::u32x4 *>(base + o);
-        st.slots = base + o + align256(16 * (size_t)g.nseg);
+        st.info = reinterpret_cast<spz::u32x4 *>(it.d_ws);
+        st.slots = (uint8_t *)it.d_ws + align256(16 * (size_t)g.nseg);
     }
     *total = off;
     for (int c = 0; c < kClasses; ++c)

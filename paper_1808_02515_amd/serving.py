@@ -7,10 +7,12 @@ over time. The server
   preallocated arena, first-fit; nothing is allocated per request);
 * launches everything admitted so far as one batch on the next of a few HIP
   streams: all decodes of the batch in one batched call (sprintz_batch_*
-  with its plan built in arena memory by an asynchronous copy), every encode
-  as one sprintz_compress call; batches on different streams run on the
-  device at the same time, so requests that arrive while others are on the
-  GPU start without waiting for them;
+  with its plan built in arena memory by an asynchronous copy), all encodes
+  in one batched compression call (sprintz_compress_batch_*, its plan in
+  arena memory too, every request coding into its own reserved workspace);
+  batches on different streams run on the device at the same time, so
+  requests that arrive while others are on the GPU start without waiting
+  for them;
 * polls an event per batch without blocking, reports each request's latency
   (arrival to completion seen by the host) and returns its memory to the
   arena.
@@ -24,9 +26,11 @@ import bisect
 import time
 from dataclasses import dataclass, field
 
-from . import (SPZ_OK, SprintzError, dtype_code, load, make_params, spz_batch_item, spz_info,
+from . import (SPZ_OK, SprintzError, dtype_code, load, make_params, spz_batch_item, spz_compress_item, spz_info,
                sprintz_batch_create_in, sprintz_batch_decompress, sprintz_batch_destroy,
-               sprintz_batch_workspace_size, sprintz_compress, sprintz_compress_bound, sprintz_workspace_size)
+               sprintz_batch_workspace_size, sprintz_compress_batch, sprintz_compress_batch_create_in,
+               sprintz_compress_batch_destroy, sprintz_compress_batch_workspace_size, sprintz_compress_bound,
+               sprintz_workspace_size)
 
 ALIGN = 256
 
@@ -107,6 +111,7 @@ class _Batch:
     event: object
     reqs: list
     plan: int | None
+    cplan: int | None    # compression plan of the batch's encodes
     allocs: tuple        # the batch's region of the metadata arena
     status_off: int      # its offset: status words, output sizes, plan tables
 
@@ -170,7 +175,22 @@ class Server:
                 items.append(spz_batch_item(r.container.data_ptr(), r.container.numel(), self.pool.base + off, nb))
                 infos.append(r.info)
             wsz = sprintz_batch_workspace_size(items, infos) if decs else 0
-            meta = self.meta.alloc(16 * n + 16 + wsz)
+            encs = [(i, r) for i, r in enumerate(reqs) if r.kind == "encode"]
+            citems = []
+            for i, r in encs:
+                rows, D = r.x.shape
+                dt = dtype_code(r.x)
+                p = make_params(r.forecaster, r.seg_rows)
+                cap = sprintz_compress_bound(rows, D, dt, p)
+                off, _ = r.allocs[0]
+                dst = self.pool.base + off
+                ws = dst + (cap + ALIGN - 1) // ALIGN * ALIGN
+                # d_out_size is set below, once the batch's metadata is placed (8 is a
+                # stand-in that only sizes the plan)
+                citems.append(spz_compress_item(r.x.data_ptr(), rows, D, dt, p, dst, cap, 8, ws,
+                                                sprintz_workspace_size(rows, D, dt, p)))
+            cwsz = sprintz_compress_batch_workspace_size(citems) if encs else 0
+            meta = self.meta.alloc(16 * n + 16 + (wsz + ALIGN - 1) // ALIGN * ALIGN + ALIGN + cwsz)
             if meta is not None:
                 break
             if n == 1:
@@ -188,8 +208,7 @@ class Server:
         ws_off = meta[0] + 16 * n + 16
         with torch.cuda.stream(s):
             self.meta.view(meta[0], 16 * n + 16).zero_()
-        allocs = []
-        plan = None
+        plan = cplan = None
         if decs:
             for r in decs:
                 r.result = (r.allocs[0][0], r.info.rows * r.info.D * (r.info.w // 8))
@@ -197,25 +216,21 @@ class Server:
             rc = sprintz_batch_decompress(plan, st_ptr, sh)
             if rc != SPZ_OK:
                 raise SprintzError(rc, "sprintz_batch_decompress")
-        for i, r in enumerate(reqs):
-            if r.kind != "encode":
-                continue
-            rows, D = r.x.shape
-            dt = dtype_code(r.x)
-            p = make_params(r.forecaster, r.seg_rows)
-            cap = sprintz_compress_bound(rows, D, dt, p)
-            off, _ = r.allocs[0]
-            dst = self.pool.base + off
-            ws = dst + (cap + ALIGN - 1) // ALIGN * ALIGN
-            wsz = sprintz_workspace_size(rows, D, dt, p)
-            rc = sprintz_compress(r.x.data_ptr(), rows, D, dt, p, dst, cap, self.meta.base + sz_off + 8 * i, ws, wsz,
-                                  st_ptr + 4 * i, sh)
+        if encs:
+            # the encodes' status words and sizes follow the decodes' (item k of
+            # the compression batch is request encs[k][0])
+            k0 = encs[0][0]
+            for k, (i, r) in enumerate(encs):
+                citems[k].d_out_size = self.meta.base + sz_off + 8 * i
+                r.result = (r.allocs[0][0], 0)
+            cws = self.meta.base + (ws_off + (wsz + ALIGN - 1) // ALIGN * ALIGN + ALIGN - 1) // ALIGN * ALIGN
+            cplan = sprintz_compress_batch_create_in(citems, cws, max(cwsz, 16), sh)
+            rc = sprintz_compress_batch(cplan, st_ptr + 4 * k0, sh)
             if rc != SPZ_OK:
-                raise SprintzError(rc, "sprintz_compress")
-            r.result = (off, 0)
+                raise SprintzError(rc, "sprintz_compress_batch")
         ev = torch.cuda.Event()
         ev.record(s)
-        self.inflight.append(_Batch(s, ev, reqs, plan, meta, meta[0]))
+        self.inflight.append(_Batch(s, ev, reqs, plan, cplan, meta, meta[0]))
 
     # -- completion ------------------------------------------------------------
     def _poll(self) -> bool:
@@ -254,6 +269,8 @@ class Server:
                 r.allocs = []
             if b.plan is not None:
                 sprintz_batch_destroy(b.plan)
+            if b.cplan is not None:
+                sprintz_compress_batch_destroy(b.cplan)
             self.meta.release(*b.allocs)
         self.inflight = keep
         return progressed
