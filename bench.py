@@ -56,6 +56,45 @@ def measured_traffic(kernel: str, workload: str):
     return e.get("bytes_per_launch")
 
 
+def host_description() -> dict:
+    """CPU model (from /proc/cpuinfo, as lscpu reports it), logical CPUs and
+    the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline_all_cores(x, forecaster, seg_rows, threads):
+    """The CPU oracle on `threads` threads over independent parts of the
+    stream (whole segments each, so the segments are those of the whole
+    stream): wall time of compressing all parts, then of decompressing them.
+    ctypes releases the interpreter lock during the oracle's calls."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    rows = x.shape[0]
+    per = -(-rows // threads)
+    per = -(-per // seg_rows) * seg_rows
+    parts = [x[k:k + per] for k in range(0, rows, per)]
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        t0 = time.perf_counter()
+        blobs = list(pool.map(lambda p: oracle.compress(p, forecaster, seg_rows), parts))
+        enc = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ys = list(pool.map(oracle.decompress, blobs))
+        dec = time.perf_counter() - t0
+    assert all(np.array_equal(y, p) for y, p in zip(ys, parts))
+    return dec, enc, len(parts)
+
+
 def cpu_baseline(x, forecaster, seg_rows, budget_s=20.0):
     """The CPU oracle on this host (1 thread): decode and encode of the same
     stream, best of up to 3 runs within the time budget."""
@@ -86,10 +125,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--forecaster", default="fire", choices=["fire", "delta"])
     ap.add_argument("--seg-rows", type=int, default=1024,
-                    help="stream workload: rows per segment; 0 = autotuned among 512, 1024, 2048 (fastest "
-                         "within 1 %% of the ratio of 2^20-row segments, else the smallest container)")
+                    help="stream workload: rows per segment; 0 = the library's autotuner (sprintz_autotune)")
     ap.add_argument("--rotate", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-sample", action="store_true",
+                    help="batch workload: skip comparing sampled containers with the oracle's bytes")
     ap.add_argument("--workload", default="stream",
                     choices=["stream", "batch", "serve", "dsweep", "huffman", "latency"],
                     help="stream: the 4,194,304 x 8 uint16 stream; batch: the many-stream batch; "
@@ -150,18 +190,29 @@ def main():
     U = x_np.nbytes
     tune = None
     if args.seg_rows == 0:
-        args.seg_rows, tune = tune_stream_seg_rows(torch.from_numpy(x_np).to(dev), args.forecaster, spz)
-        print(f"[bench] seg_rows {args.seg_rows} ({tune})", file=sys.stderr, flush=True)
+        xt = torch.from_numpy(x_np).to(dev)
+        args.seg_rows = spz.sprintz_autotune(xt.data_ptr(), rows, D, spz.SPZ_UINT16, spz.make_params(args.forecaster, 0),
+                                             torch.cuda.current_stream().cuda_stream)
+        tune = "library autotuner (sprintz_autotune)"
+        del xt
+        print(f"[bench] seg_rows {args.seg_rows} (autotuned)", file=sys.stderr, flush=True)
     workload = stream_workload_name(rows, D, args.forecaster, args.seg_rows)
 
     base_blob = cpu = None
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         base_blob, cpu_dec_s, cpu_enc_s, ndec, nenc = cpu_baseline(x_np, args.forecaster, args.seg_rows)
+        host = host_description()
+        threads = max(1, min(host["usable_cpus"], 16))
+        all_dec_s, all_enc_s, nparts = cpu_baseline_all_cores(x_np, args.forecaster, args.seg_rows, threads)
         cpu = {"value": round(U / cpu_dec_s / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
                "sample": f"the full {rows}x{D} uint16 stream ({U} B), decode best of {ndec}; "
                          f"encode {U / cpu_enc_s / 1e9:.4f} GB/s best of {nenc}",
-               "encode_GBps": round(U / cpu_enc_s / 1e9, 4)}
+               "encode_GBps": round(U / cpu_enc_s / 1e9, 4),
+               "all_cores": {"cores": threads, "decode_GBps": round(U / all_dec_s / 1e9, 4),
+                             "encode_GBps": round(U / all_enc_s / 1e9, 4),
+                             "sample": f"the same stream in {nparts} parts of whole segments, one thread each"},
+               **host}
 
     p = spz.make_params(args.forecaster, args.seg_rows)
     R = args.rotate
@@ -258,6 +309,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_decode_pc", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": algo_bytes},
+        "roofline_encode": {"bound": "hbm", "kernels": "k_encode_sp + k_enc_scan + k_enc_compact (one call)",
+                            "achieved": round(algo_bytes / enc_mean / 1e9, 2), "peak": HBM_PEAK_GBPS,
+                            "unit": "GB/s", "frac": round(algo_bytes / enc_mean / 1e9 / HBM_PEAK_GBPS, 4),
+                            "traffic": measured_traffic("encode", workload),
+                            "algorithmic_bytes_per_call": algo_bytes},
         "cpu_baseline": cpu,
         "paper_context": "paper: >3 GB/s single-thread decompression on an Intel i7-4960HQ (2.6 GHz, AVX2)",
     }
@@ -268,61 +324,13 @@ def main():
         bargs.streams, bargs.steps, bargs.warmup, bargs.no_cpu_baseline = args.batch_streams, 5, 2, True
         b = run_batch(bargs)
         out["batched_vs_plain"] = {k: b[k] for k in (
-            "batch_decode_GBps", "per_stream_decode_GBps", "batched_vs_per_stream", "graph_decode_GBps",
-            "u16_fire_decode_GBps", "u16_fire_hbm_frac", "compression_ratio", "parity")}
+            "batch_decode_GBps", "per_stream_decode_GBps", "batched_vs_per_stream", "per_stream_graph_decode_GBps",
+            "batched_vs_per_stream_graph", "graph_decode_GBps", "batch_encode_GBps", "per_stream_encode_GBps",
+            "encode_batched_vs_per_stream", "u16_fire_decode_GBps", "u16_fire_hbm_frac", "compression_ratio",
+            "parity", "roofline")}
         out["batched_vs_plain"]["workload"] = b["config"]["workload"]
+        out["batched_vs_plain"]["seg_rows_per_class"] = b["config"]["seg_rows_per_class"]
     print(json.dumps(out), flush=True)
-
-
-def pick_seg_rows(sizes: dict, times: dict, ref_bytes: int, tol: float = 0.01) -> int:
-    """The autotuner's rule. sizes and times map each candidate seg_rows to
-    its compressed bytes and decode time. Among the candidates whose container
-    is at most (1 + tol) x ref_bytes (the unsegmented container), take the
-    fastest; if none qualifies, take the smallest container. Ties go to the
-    candidate listed first."""
-    ok = [S for S in sizes if sizes[S] <= (1 + tol) * ref_bytes]
-    if ok:
-        return min(ok, key=lambda S: times[S])
-    return min(sizes, key=lambda S: sizes[S])
-
-
-def tune_stream_seg_rows(x, forecaster, spz, cands=(512, 1024, 2048), ref_rows=1 << 20):
-    """seg_rows for one stream: the fastest decode among the candidates whose
-    container stays within 1 % of the one with ref_rows-row segments (close
-    to the paper's unsegmented stream); if none does, the smallest container.
-    Returns (seg_rows, {seg_rows: [bytes, best decode us]})."""
-    import torch
-    rows, D = x.shape
-    dt = spz.dtype_code(x)
-    sh = torch.cuda.current_stream().cuda_stream
-    table = {}
-    for S in (ref_rows,) + tuple(cands):
-        enc = spz.Encoder.create(rows, D, dt, spz.make_params(forecaster, S), device=x.device)
-        enc.run(x)
-        torch.cuda.synchronize()
-        csize = int(enc.out_size.item())
-        info = spz.info_of(enc.dst[:64])
-        y = torch.empty_like(x)
-        st = torch.zeros(1, dtype=torch.int32, device=x.device)
-        best = float("inf")
-        for k in range(6):
-            a, b = _events(1)[0]
-            a.record()
-            rc = spz.sprintz_decompress(enc.dst.data_ptr(), csize, info, y.data_ptr(), x.numel() * x.element_size(),
-                                        st.data_ptr(), sh)
-            b.record()
-            if rc != spz.SPZ_OK:
-                raise spz.SprintzError(rc, "sprintz_decompress")
-            torch.cuda.synchronize()
-            if k:
-                best = min(best, a.elapsed_time(b) * 1e3)
-        if not torch.equal(x, y) or int(st.item()) != 0:
-            print(f"[bench] PARITY FAILURE while tuning seg_rows {S}", file=sys.stderr, flush=True)
-            sys.exit(1)
-        table[S] = [csize, round(best, 2)]
-        del enc, y
-    pick = pick_seg_rows({S: table[S][0] for S in cands}, {S: table[S][1] for S in cands}, table[ref_rows][0])
-    return pick, {str(k): v for k, v in table.items()}
 
 
 def _events(n):
@@ -330,48 +338,16 @@ def _events(n):
     return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
 
 
-def autotune_seg_rows(streams, spz, cands=(256, 512, 1024, 2048), per_class=6, inf_rows=1 << 20):
-    """Pick seg_rows per (dtype, D) class on a sample of its streams: the
-    fastest batched decode among the candidates whose compressed size stays
-    within 1 % of one segment per stream (seg_rows = 2^20, the unsegmented
-    paper form); if none does, the smallest. Returns {class: (S, table)}."""
-    import torch
-    classes = {}
-    for k, x in enumerate(streams):
-        classes.setdefault((x.element_size(), x.shape[1]), []).append(k)
-    out = {}
-    for key, ks in sorted(classes.items()):
-        sample = ks[:per_class]
-        ref = sum(spz.compress(streams[k], "fire", inf_rows).numel() for k in sample)
-        rows_tab = []
-        for S in cands:
-            conts = [spz.compress(streams[k], "fire", S) for k in sample]
-            csz = sum(c.numel() for c in conts)
-            bd = spz.BatchDecoder(conts)
-            bd.run()
-            torch.cuda.synchronize()
-            ev = _events(3)
-            for a, b in ev:
-                a.record()
-                bd.run()
-                b.record()
-            torch.cuda.synchronize()
-            t = min(a.elapsed_time(b) for a, b in ev)
-            bd.close()
-            rows_tab.append({"seg_rows": S, "bytes": csz, "loss_vs_unsegmented": round(csz / ref - 1, 4),
-                             "decode_ms": round(t, 4)})
-        pick = pick_seg_rows({r["seg_rows"]: r["bytes"] for r in rows_tab},
-                             {r["seg_rows"]: r["decode_ms"] for r in rows_tab}, ref)
-        out[key] = (pick, rows_tab)
-    return out
-
-
 def run_batch(args):
-    """The many-stream workload: streams drawn on the GPU, compressed with
-    autotuned seg_rows, then decoded (a) in one batched call per class work
-    list, (b) as one captured HIP graph of that call, (c) one
-    sprintz_decompress launch per stream. Every output is compared with its
-    input; sampled containers are compared with the CPU oracle's bytes."""
+    """The many-stream workload: streams drawn on the GPU; segment sizes from
+    the library's autotuner (once per class dtype x D); compression (a) in
+    one batched call (sprintz_compress_batch) and (b) one sprintz_compress
+    launch per stream; decompression (a) in one batched call per class work
+    list, (b) as a captured HIP graph of that call, (c) one
+    sprintz_decompress launch per stream, eager and (d) captured as one
+    graph of all those launches (no host overhead). Every output is
+    compared with its input; a deterministic sample of containers with the
+    CPU oracle's bytes."""
     import torch
     import datagen
     import oracle
@@ -382,14 +358,46 @@ def run_batch(args):
     streams = [datagen.batch_stream_torch(k) for k in range(n)]
     torch.cuda.synchronize()
     print(f"[bench] drew {n} streams in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    tune = autotune_seg_rows(streams, spz)
-    print(f"[bench] seg_rows per class: { {str(k): v[0] for k, v in tune.items()} }", file=sys.stderr, flush=True)
-    t0 = time.time()
-    conts = [spz.compress(x, args.forecaster, tune[(x.element_size(), x.shape[1])][0]) for x in streams]
-    torch.cuda.synchronize()
-    print(f"[bench] compressed in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     U = sum(x.numel() * x.element_size() for x in streams)
+    reps = max(args.steps, 1)
+    sh = torch.cuda.current_stream().cuda_stream
+
+    # ---- compression: batched vs one call per stream ---------------------------
+    t0 = time.time()
+    be = spz.BatchEncoder(streams, args.forecaster, 0)
+    print(f"[bench] tuned seg_rows per class {be.tuned} and planned in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    for _ in range(max(args.warmup, 1)):
+        be.run()
+    torch.cuda.synchronize()
+    ev = _events(reps)
+    for a, b in ev:
+        a.record()
+        be.run()
+        b.record()
+    torch.cuda.synchronize()
+    enc_batch_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    conts = be.containers()
+    ok_all = int(be.status.abs().sum().item()) == 0
+    encs = [spz.Encoder.create(x.shape[0], x.shape[1], spz.dtype_code(x), p) for x, p in zip(streams, be.params)]
+
+    def enc_per_stream():
+        for e, x in zip(encs, streams):
+            e.run(x)
+    enc_per_stream()
+    torch.cuda.synchronize()
+    a, b = _events(1)[0]
+    a.record()
+    enc_per_stream()
+    b.record()
+    torch.cuda.synchronize()
+    enc_per_ms = a.elapsed_time(b)
+    for k in range(0, n, max(1, n // 200)):       # the two forms give the same bytes
+        ok_all = ok_all and torch.equal(encs[k].dst[: int(encs[k].out_size.item())], conts[k])
+    del encs
     C = sum(c.numel() for c in conts)
+    print(f"[bench] encode batched {enc_batch_ms:.2f} ms vs per stream {enc_per_ms:.2f} ms", file=sys.stderr,
+          flush=True)
 
     def timed_batch(idx, reps):
         bd = spz.BatchDecoder([conts[k] for k in idx])
@@ -407,9 +415,9 @@ def run_batch(args):
             torch.equal(o.view(torch.uint8), streams[k].view(torch.uint8)) for o, k in zip(bd.outs, idx))
         return bd, float(np.mean(ms)), min(ms), good
 
-    reps = max(args.steps, 1)
     allk = list(range(n))
-    bd, all_ms, all_best, ok_all = timed_batch(allk, reps)
+    bd, all_ms, all_best, ok = timed_batch(allk, reps)
+    ok_all = ok_all and ok
     # the same call captured once as a HIP graph and replayed
     s = torch.cuda.Stream()
     g = torch.cuda.CUDAGraph()
@@ -425,28 +433,40 @@ def run_batch(args):
     torch.cuda.synchronize()
     graph_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     ok_all = ok_all and all(torch.equal(o.view(torch.uint8), streams[k].view(torch.uint8)) for k, o in enumerate(bd.outs))
-    # one launch per stream
-    sh = torch.cuda.current_stream().cuda_stream
+    # one launch per stream: eager, and all launches captured in one graph
     st = torch.zeros(n, dtype=torch.int32, device="cuda")
 
-    def per_stream():
+    def per_stream(stream_handle):
         for k in range(n):
             o = bd.outs[k]
             rc = spz.sprintz_decompress(conts[k].data_ptr(), conts[k].numel(), bd.infos[k], o.data_ptr(),
-                                        o.numel() * o.element_size(), st[k:k + 1].data_ptr(), sh)
+                                        o.numel() * o.element_size(), st[k:k + 1].data_ptr(), stream_handle)
             if rc != spz.SPZ_OK:
                 raise spz.SprintzError(rc, "sprintz_decompress")
-    per_stream()
+    per_stream(sh)
     torch.cuda.synchronize()
     a, b = _events(1)[0]
     a.record()
-    per_stream()
+    per_stream(sh)
     b.record()
     torch.cuda.synchronize()
     per_ms = a.elapsed_time(b)
+    gp = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gp, stream=s):
+        per_stream(s.cuda_stream)
+    gp.replay()
+    torch.cuda.synchronize()
+    ev = _events(3)
+    for a, b in ev:
+        a.record()
+        gp.replay()
+        b.record()
+    torch.cuda.synchronize()
+    per_graph_ms = min(a.elapsed_time(b) for a, b in ev)
     ok_all = ok_all and int(st.abs().sum().item()) == 0
+    ok_all = ok_all and all(torch.equal(o.view(torch.uint8), streams[k].view(torch.uint8)) for k, o in enumerate(bd.outs))
     bd.close()
-    del bd, g
+    del bd, g, gp
     # 16-bit FIRE sub-batch
     k16 = [k for k in allk if streams[k].element_size() == 2]
     U16 = sum(streams[k].numel() * 2 for k in k16)
@@ -454,37 +474,36 @@ def run_batch(args):
     bd16, ms16, best16, ok16 = timed_batch(k16, reps)
     bd16.close()
     if not (ok_all and ok16):
-        print("[bench] PARITY FAILURE (round trip)", file=sys.stderr, flush=True)
+        print("[bench] PARITY FAILURE (round trip or batched/per-stream bytes)", file=sys.stderr, flush=True)
         sys.exit(1)
-    # CPU oracle leg: container bytes of a deterministic sample of streams
-    # (every n/40-th, at most 2M samples each) compared with the oracle's,
-    # then the oracle timed on a bounded sample of the same streams (~20 s)
-    cpu = None
+    # container bytes of a deterministic sample of streams (every n/40-th, at
+    # most 2M samples each) against the CPU oracle's
     parity = 0
-    if not args.no_cpu_baseline:
+    if not args.no_oracle_sample:
         for k in range(0, n, max(1, n // 40)):
             x = streams[k]
             if x.numel() > 2_000_000:
                 continue
-            xn = x.cpu().numpy()   # int8 or int16 (the uint16 bit patterns; same container bytes but byte 7)
-            ref = oracle.compress(xn, args.forecaster, tune[(x.element_size(), x.shape[1])][0])
-            if conts[k].cpu().numpy().tobytes() != ref:
+            S = int.from_bytes(conts[k][24:28].cpu().numpy().tobytes(), "little")
+            if conts[k].cpu().numpy().tobytes() != oracle.compress(x.cpu().numpy(), args.forecaster, S):
                 print(f"[bench] PARITY FAILURE (container bytes) stream {k}", file=sys.stderr, flush=True)
                 sys.exit(1)
             parity += 1
+    cpu = None
+    if not args.no_cpu_baseline:
         done, secs = 0, 0.0
         for k in range(n):
             if secs > 20.0:
                 break
-            x = streams[k]
-            xn = x.cpu().numpy()
             blob = conts[k].cpu().numpy().tobytes()
             t1 = time.perf_counter()
             oracle.decompress(blob)
             secs += time.perf_counter() - t1
-            done += xn.nbytes
+            done += streams[k].numel() * streams[k].element_size()
         cpu = {"value": round(done / secs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
                "sample": f"the first streams of the batch up to 20 s of decoding ({done} B)"}
+    key16 = f"{n} streams u16 fire sub-batch"
+    achieved16 = (U16 + C16) / (ms16 * 1e-3) / 1e9
     out = {
         "metric": "decode GB/s and encode GB/s (uncompressed bytes), % HBM peak, batched vs plain",
         "value": round(U / (all_ms * 1e-3) / 1e9, 2),
@@ -501,26 +520,35 @@ def run_batch(args):
         "config": {"workload": f"batch of {n} streams: rows log-uniform 1e3..1e6, D in {{1,2,4,8,16}}, "
                                f"int8 walks and uint16 AR(2), {args.forecaster}", "streams": n,
                    "uncompressed_bytes": U, "compressed_bytes": C, "launch": "batched (per-class persistent grids)",
-                   "seg_rows_per_class": {f"{8 * k[0]}bit_D{k[1]}": v[0] for k, v in tune.items()}},
+                   "seg_rows_per_class": {f"{8 * (2 if k[0] >= 3 else 1)}bit_D{k[1]}": v
+                                          for k, v in sorted(be.tuned.items())},
+                   "seg_rows_tuning": "library autotuner (sprintz_autotune) on each class's longest stream"},
         "batch_decode_GBps": round(U / (all_ms * 1e-3) / 1e9, 2),
         "batch_decode_best_ms": round(all_best, 4),
         "graph_replay_ms": round(graph_ms, 4),
         "graph_decode_GBps": round(U / (graph_ms * 1e-3) / 1e9, 2),
         "per_stream_launch_ms": round(per_ms, 4),
         "per_stream_decode_GBps": round(U / (per_ms * 1e-3) / 1e9, 2),
+        "per_stream_graph_ms": round(per_graph_ms, 4),
+        "per_stream_graph_decode_GBps": round(U / (per_graph_ms * 1e-3) / 1e9, 2),
         "batched_vs_per_stream": round(per_ms / all_ms, 2),
+        "batched_vs_per_stream_graph": round(per_graph_ms / all_ms, 2),
+        "batch_encode_GBps": round(U / (enc_batch_ms * 1e-3) / 1e9, 2),
+        "per_stream_encode_GBps": round(U / (enc_per_ms * 1e-3) / 1e9, 2),
+        "encode_batched_vs_per_stream": round(enc_per_ms / enc_batch_ms, 2),
         "u16_fire_streams": len(k16),
         "u16_fire_decode_GBps": round(U16 / (ms16 * 1e-3) / 1e9, 2),
-        "u16_fire_hbm_frac": round((U16 + C16) / (ms16 * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "u16_fire_hbm_frac": round(achieved16 / HBM_PEAK_GBPS, 4),
         "compression_ratio": round(U / C, 4),
-        "parity": f"round trip exact on all {n} streams (batched, graph and per-stream); "
+        "parity": f"round trip exact on all {n} streams (batched, graph, per-stream and per-stream graph); "
+                  "batched and per-stream compression give equal containers on a sample of 200; "
                   + (f"container bytes equal to the CPU oracle on {parity} sampled streams" if parity
-                     else "oracle leg not run here"),
-        "roofline": {"bound": "hbm", "kernel": "k_decode_pc_batch", "achieved": round((U + C) / (all_ms * 1e-3) / 1e9, 2),
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round((U + C) / (all_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4), "traffic": None,
-                     "algorithmic_bytes_per_launch": U + C},
-        "autotune": {f"{8 * k[0]}bit_D{k[1]}": v[1] for k, v in tune.items()},
+                     else "oracle sample not run here"),
+        "roofline": {"bound": "hbm", "kernel": "k_decode_pc_batch", "workload": key16,
+                     "achieved": round(achieved16, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved16 / HBM_PEAK_GBPS, 4),
+                     "traffic": measured_traffic("k_decode_pc_batch", key16),
+                     "algorithmic_bytes_per_launch": U16 + C16},
         "cpu_baseline": cpu,
     }
     return out

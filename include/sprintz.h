@@ -132,9 +132,11 @@ spz_status sprintz_compress(const void *d_src, uint64_t rows, uint32_t D, spz_dt
  * rows of d_src at the reference segment size (one segment over them, the
  * paper's unsegmented stream) and at each candidate 256, 512, 1024, 2048 and
  * 4096 below it, and times the decoding of each container (best of three,
- * HIP events). The choice is the fastest decode among the sizes whose
- * container stays within 1 % of the reference's bytes; if none does, the
- * smallest container. Only the segment size is searched: waves per segment
+ * HIP events). The reference only sets the bar: the choice is the fastest
+ * decode among the candidates whose container stays within 1 % of the
+ * reference's bytes; if none does, the candidate with the smallest container
+ * (its loss is above 1 %); the reference itself only when there is no
+ * candidate below it. Only the segment size is searched: waves per segment
  * and LDS tiles are fixed by the kernels. The result goes to *seg_rows_out
  * and to a host cache (mutex-protected, keyed by D, w, forecaster,
  * learn_shift, hdr_group, entropy and the power-of-two size class of the

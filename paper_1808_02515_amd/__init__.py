@@ -427,22 +427,29 @@ class BatchEncoder:
     """A compression plan over many (rows, D) CUDA tensors: one call codes
     them all (per-class persistent launches over the series' segments, one
     offset scan per series, one compaction launch). Containers go to
-    ``self.dsts`` (each at its bound); ``sizes()`` returns their byte counts.
-    The plan keeps pointers to the inputs: keep them alive while it is used.
-    seg_rows 0 is resolved here per series with the library's autotuner."""
+    ``self.dsts`` (each at its bound); ``containers()`` returns them at their
+    sizes. The plan keeps pointers to the inputs: keep them alive while it is
+    used. With seg_rows 0 the library's autotuner runs once per class
+    (dtype, D), on the class's longest series, and its choice
+    (``self.tuned``) codes the whole class."""
 
     def __init__(self, xs, forecaster: str = "fire", seg_rows: int = 1024, learn_shift: int = 1, device="cuda",
                  stream=None):
         torch = _torch()
         self.xs = [x if x.dim() == 2 else x.reshape(-1, 1) for x in xs]
         sh = _stream_handle(stream)
-        self.params = []
-        for x in self.xs:
-            S = seg_rows
-            if S == 0:
-                S = sprintz_autotune(x.data_ptr(), x.shape[0], x.shape[1], dtype_code(x),
-                                     make_params(forecaster, 0, 0, learn_shift), sh)
-            self.params.append(make_params(forecaster, S, 0, learn_shift))
+        self.tuned = {}
+        if seg_rows == 0:
+            longest = {}
+            for x in self.xs:
+                key = (dtype_code(x), x.shape[1])
+                if key not in longest or x.shape[0] > longest[key].shape[0]:
+                    longest[key] = x
+            for key, x in sorted(longest.items()):
+                self.tuned[key] = sprintz_autotune(x.data_ptr(), x.shape[0], x.shape[1], key[0],
+                                                   make_params(forecaster, 0, 0, learn_shift), sh)
+        self.params = [make_params(forecaster, self.tuned[(dtype_code(x), x.shape[1])] if seg_rows == 0 else seg_rows,
+                                   0, learn_shift) for x in self.xs]
         self.dsts = [torch.empty(sprintz_compress_bound(x.shape[0], x.shape[1], dtype_code(x), p), dtype=torch.uint8,
                                  device=device) for x, p in zip(self.xs, self.params)]
         self.out_sizes = torch.zeros(max(len(self.xs), 1), dtype=torch.int64, device=device)

@@ -409,17 +409,20 @@ TuneKey tune_key(uint64_t rows, uint32_t D, uint32_t w, const spz_params *p) {
     return TuneKey{D, w, p->forecaster, p->learn_shift, p->hdr_group, p->entropy, 32u - (uint32_t)__builtin_clz(ref)};
 }
 
-// The choice rule: among the candidates whose container is at most 1 % above
-// the reference (cands[0]), the fastest decode; if none qualifies, the
-// smallest container. Ties go to the candidate listed first.
+// The choice rule: the reference (cands[0], one segment) only sets the bar.
+// Among the other candidates, those whose container is at most 1 % above the
+// reference's, the fastest decode; if none qualifies, the smallest container
+// (its loss is then above 1 %). Ties go to the candidate listed first. With
+// no other candidate, the reference.
 uint32_t tune_pick(const std::vector<uint32_t> &cands, const std::vector<uint64_t> &bytes,
                    const std::vector<float> &ms) {
+    if (cands.size() == 1) return cands[0];
     int best = -1;
-    for (size_t k = 0; k < cands.size(); ++k)
+    for (size_t k = 1; k < cands.size(); ++k)
         if (bytes[k] * 100 <= bytes[0] * 101 && (best < 0 || ms[k] < ms[best])) best = (int)k;
     if (best >= 0) return cands[best];
-    size_t small = 0;
-    for (size_t k = 1; k < cands.size(); ++k)
+    size_t small = 1;
+    for (size_t k = 2; k < cands.size(); ++k)
         if (bytes[k] < bytes[small]) small = k;
     return cands[small];
 }

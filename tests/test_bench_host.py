@@ -1,5 +1,6 @@
-"""Host-side logic of the benchmark script: the seg_rows autotuner's choice
-rule and the single-GPU guard. No GPU is used."""
+"""Host-side logic of the benchmark script: host description, the
+all-core CPU baseline, the single-GPU guard and the counter-summary keys. No
+GPU is used."""
 import os
 import subprocess
 import sys
@@ -12,31 +13,17 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def test_pick_fastest_within_tolerance():
-    sizes = {256: 1100, 512: 1009, 1024: 1005, 2048: 1001}
-    times = {256: 1.0, 512: 2.0, 1024: 3.0, 2048: 4.0}
-    # 256 is fastest but 10 % larger than the unsegmented 1000 bytes
-    assert bench.pick_seg_rows(sizes, times, 1000) == 512
+def test_host_description():
+    h = bench.host_description()
+    assert h["nproc"] >= 1 and 1 <= h["usable_cpus"] <= h["nproc"] and isinstance(h["cpu_model"], str)
 
 
-def test_pick_boundary_is_inclusive():
-    sizes = {512: 1010, 1024: 1000}
-    times = {512: 1.0, 1024: 2.0}
-    assert bench.pick_seg_rows(sizes, times, 1000) == 512
-    assert bench.pick_seg_rows({512: 1011, 1024: 1000}, times, 1000) == 1024
-
-
-def test_pick_smallest_container_when_none_qualifies():
-    sizes = {256: 1300, 512: 1200, 1024: 1150, 2048: 1160}
-    times = {256: 1.0, 512: 2.0, 1024: 3.0, 2048: 0.5}
-    assert bench.pick_seg_rows(sizes, times, 1000) == 1024
-
-
-def test_pick_ties_go_to_first_listed():
-    sizes = {512: 1000, 1024: 1000}
-    times = {512: 1.0, 1024: 1.0}
-    assert bench.pick_seg_rows(sizes, times, 1000) == 512
-    assert bench.pick_seg_rows({1024: 1000, 512: 1000}, times, 1000) == 1024
+def test_all_core_baseline_splits_whole_segments():
+    # parts of whole segments on several threads round-trip exactly
+    import datagen
+    x = datagen.ar2_uint16(50_003, 3, seed=7)
+    dec, enc, parts = bench.cpu_baseline_all_cores(x, "fire", 1024, 4)
+    assert parts == 4 and dec > 0 and enc > 0
 
 
 @pytest.mark.parametrize("n", [2, 8])
