@@ -32,7 +32,7 @@
  *   - int8/uint8 (and int16/uint16) produce identical bytes: the codec works
  *     on w-bit patterns modulo 2^w. The dtype is recorded only so that the
  *     decoder can report it.
- *   - GPU limits: 1 <= D <= 64, 8 <= seg_rows <= 2^20 with seg_rows % 8 == 0,
+ *   - GPU limits: 1 <= D <= 128, 8 <= seg_rows <= 2^20 with seg_rows % 8 == 0,
  *     hdr_group <= 255, learn_shift <= 8. Outside them the call returns
  *     SPZ_EUNSUPPORTED (D) or SPZ_EINVAL (the rest).
  */

@@ -24,7 +24,7 @@
 
 namespace {
 
-constexpr uint32_t kMaxD = 64;
+constexpr uint32_t kMaxD = 128;
 constexpr uint32_t kMaxSegRows = 1u << 20;
 constexpr size_t kHeader = 64;
 
@@ -87,8 +87,9 @@ spz::Geom make_geom(uint64_t rows, uint32_t D, uint32_t w, uint32_t S, uint32_t 
     return g;
 }
 
+// Walker kernels: one lane group of min(Dp, 64) lanes per segment.
 uint32_t grid_for(const spz::Geom &g) {
-    uint64_t lanes = (uint64_t)g.nseg << g.dp_log2;
+    uint64_t lanes = (uint64_t)g.nseg << std::min<uint32_t>(g.dp_log2, 6);
     return (uint32_t)((lanes + spz::kThreads - 1) / spz::kThreads);
 }
 
@@ -97,7 +98,7 @@ uint32_t grid_for(const spz::Geom &g) {
 // header arrays and chunk payloads inside its LDS staging buffers; anything
 // else goes through the per-lane walker.
 bool enc_chunked_ok(const spz::Geom &g, uint32_t w, const void *src) {
-    if (g.G != 0 || ((uintptr_t)src & 15) || ((uint64_t)g.S * g.D * (w / 8)) % 16 != 0) return false;
+    if (g.G != 0 || g.D > 64 || ((uintptr_t)src & 15) || ((uint64_t)g.S * g.D * (w / 8)) % 16 != 0) return false;
     const uint32_t spw = 64u >> g.dp_log2;
     const uint32_t cb = spz::enc_chunk_blocks(g.dp_log2);
     const uint64_t hdr_seg = (spz::enc_hdr_cap(g.S >> 3, g.D, w) + 15) & ~15ull;
@@ -1202,7 +1203,7 @@ const char *sprintz_strerror(spz_status s) {
         case SPZ_EINVAL: return "invalid argument";
         case SPZ_ENOSPC: return "destination or workspace too small";
         case SPZ_ECORRUPT: return "corrupt container header";
-        case SPZ_EUNSUPPORTED: return "outside the GPU limits (D <= 64)";
+        case SPZ_EUNSUPPORTED: return "outside the GPU limits (D <= 128)";
         case SPZ_EHIP: return "HIP runtime error";
         case SPZ_ENOMEM: return "out of memory";
         default: return "unknown status";

@@ -6,10 +6,12 @@
 // with the encoder, which also trains on those rows). Otherwise the payload
 // is unpacked with the per-column widths of Section 4.3 and x = err + x_hat.
 //
-// One lane per (segment, column); a lane walks its segment's records in
-// order, so header groups of any size need no extra pass. Every read of the
-// container is clamped inside the segment's extent, so a corrupt container
-// can only produce wrong samples and a status bit, never a stray access.
+// One lane per (segment, column), or per two columns j and j + 64 when D
+// exceeds 64 (a segment's lane group never outgrows a wavefront); a lane
+// walks its segment's records in order, so header groups of any size need
+// no extra pass. Every read of the container is clamped inside the segment's
+// extent, so a corrupt container can only produce wrong samples and a status
+// bit, never a stray access.
 #pragma once
 
 #include "spz_device.h"
@@ -25,13 +27,17 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
     constexpr uint32_t WB = W / 8;
     constexpr uint32_t MASK = (1u << W) - 1;
 
-    const uint32_t Dp = 1u << g.dp_log2;
+    const uint32_t lg = min(g.dp_log2, 6u);
+    const uint32_t Dl = 1u << lg;                 // lanes of a segment
     const uint32_t gid = blockIdx.x * kThreads + threadIdx.x;
-    const uint32_t seg = gid >> g.dp_log2;
-    const uint32_t j = gid & (Dp - 1);
+    const uint32_t seg = gid >> lg;
+    const uint32_t j = gid & (Dl - 1);
     if (seg >= g.nseg) return;
-    const bool col = j < g.D;
     const uint32_t D = g.D;
+    constexpr uint32_t CPL = 2;                   // column slots of a lane: j and j + 64
+    const uint32_t ncs = D > Dl ? 2u : 1u;
+    bool col[CPL];
+    for (uint32_t c = 0; c < CPL; ++c) col[c] = c < ncs && j + 64 * c < D;
 
     const uint64_t a = ld_u64_aligned(src + 64 + 8ull * seg);
     const uint64_t b = ld_u64_aligned(src + 64 + 8ull * seg + 8);
@@ -54,7 +60,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
     const uint64_t row0 = (uint64_t)seg * g.S;
     const uint32_t nr = (uint32_t)min((uint64_t)g.S, g.rows - row0);
     const uint32_t nblk = nr >> 3, tail = nr & 7u;
-    T *out = dst + row0 * D + (col ? j : 0);
+    T *out = dst + row0 * D + j;
 
     const uint32_t nrec = segw[0];
     if (nrec > nblk) {  // every record covers at least one block
@@ -63,11 +69,11 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
     }
     uint32_t cursor = 4;        // byte position in the segment
     uint32_t r = 0, grp_left = 0, hpos = 0, rle_left = 0;
-    uint32_t width = 0, off = 0, stride = 0, p0 = 0;
+    uint32_t width[CPL] = {0, 0}, off[CPL] = {0, 0}, p0[CPL] = {0, 0}, stride = 0;
     bool is_rle = false, ok = true;
 
-    uint32_t prev = 0;
-    int32_t delta = 0, acc = 0;
+    uint32_t prev[CPL] = {0, 0};
+    int32_t delta[CPL] = {0, 0}, acc[CPL] = {0, 0};
 
     for (uint32_t blk = 0; blk < nblk; ++blk) {
         if (rle_left == 0) {
@@ -78,14 +84,19 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
                 cursor += (uint32_t)(((uint64_t)cnt * D * HB + 7) >> 3);
                 grp_left = cnt;
             }
-            const uint32_t code = col ? getbits(hpos + j * HB, HB) : 0u;
+            // the widths of the lane's columns; columns j + 64 follow all of
+            // the first 64 in the row
+            uint32_t wsum = 0;
+            for (uint32_t c = 0; c < ncs; ++c) {
+                const uint32_t code = col[c] ? getbits(hpos + (j + 64 * c) * HB, HB) : 0u;
+                width[c] = code < (uint32_t)W - 1 ? code : (uint32_t)W;
+                const uint32_t incl = group_incl_sum(width[c], Dl, j);
+                off[c] = wsum + incl - width[c];
+                wsum += group_last(incl, Dl);
+            }
             hpos += D * HB;
             grp_left--;
             r++;
-            width = code < (uint32_t)W - 1 ? code : (uint32_t)W;
-            const uint32_t incl = group_incl_sum(width, Dp, j);
-            const uint32_t wsum = group_last(incl, Dp);
-            off = incl - width;
             if (wsum == 0) {
                 const uint32_t cnt16 = getbits(cursor * 8, 16);
                 cursor += 2;
@@ -94,12 +105,12 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
                 is_rle = true;
             } else {
                 if (COLMAJOR) {
-                    p0 = (cursor + off) * 8;   // column j: width bytes, values back to back
-                    stride = width;
+                    p0[0] = (cursor + off[0]) * 8;   // column j: width bytes, values back to back
+                    stride = width[0];
                     cursor += wsum;
                 } else {
                     const uint32_t R = (wsum + 7) >> 3;  // bytes per packed row
-                    p0 = cursor * 8 + off;
+                    for (uint32_t c = 0; c < ncs; ++c) p0[c] = cursor * 8 + off[c];
                     stride = 8 * R;
                     cursor += 8 * R;
                 }
@@ -108,33 +119,36 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
             }
         }
         rle_left--;
-        const uint32_t wd = is_rle ? 0u : width;
-        const int32_t alpha = FIRE ? (acc >> g.sh) : 0;
-        int32_t grad = 0;
-        T vals[8];
+        for (uint32_t c = 0; c < ncs; ++c) {
+            const uint32_t wd = is_rle ? 0u : width[c];
+            const int32_t alpha = FIRE ? (acc[c] >> g.sh) : 0;
+            int32_t grad = 0;
+            T vals[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const uint32_t z = getbits(p0 + (uint32_t)i * stride, wd);
-            const int32_t e = unzigzag(z);
-            int32_t s = e;
-            if (FIRE) s += __mul24(alpha, delta) >> W;
-            if (FIRE && (i & 1)) grad += __mul24(sgn(e), delta);
-            if (FIRE) delta = sext<W>(s);
-            prev = (prev + (uint32_t)s) & MASK;
-            vals[i] = (T)prev;
-        }
-        if (FIRE) acc = min(max(acc + grad, g.acc_lo), g.acc_hi);
-        if (col) {
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t z = getbits(p0[c] + (uint32_t)i * stride, wd);
+                const int32_t e = unzigzag(z);
+                int32_t s = e;
+                if (FIRE) s += __mul24(alpha, delta[c]) >> W;
+                if (FIRE && (i & 1)) grad += __mul24(sgn(e), delta[c]);
+                if (FIRE) delta[c] = sext<W>(s);
+                prev[c] = (prev[c] + (uint32_t)s) & MASK;
+                vals[i] = (T)prev[c];
+            }
+            if (FIRE) acc[c] = min(max(acc[c] + grad, g.acc_lo), g.acc_hi);
+            if (col[c]) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) out[(uint64_t)(8 * blk + i) * D] = vals[i];
+                for (int i = 0; i < 8; ++i) out[(uint64_t)(8 * blk + i) * D + 64 * c] = vals[i];
+            }
         }
     }
     if (ok && (rle_left != 0 || r != nrec)) ok = false;
     if (ok) {
-        if (col) {
+        for (uint32_t c = 0; c < ncs; ++c) {
+            if (!col[c]) continue;
             for (uint32_t t = 0; t < tail; ++t) {
-                const uint32_t x = getbits((cursor + (t * D + j) * WB) * 8, W);
-                out[(uint64_t)(8 * nblk + t) * D] = (T)x;
+                const uint32_t x = getbits((cursor + (t * D + j + 64 * c) * WB) * 8, W);
+                out[(uint64_t)(8 * nblk + t) * D + 64 * c] = (T)x;
             }
         }
         cursor += tail * D * WB;

@@ -9,7 +9,9 @@
 //
 // Two passes over the same per-lane walk: pass 1 (WRITE = false) only sizes
 // every segment; a single-workgroup scan turns the sizes into the offset
-// table; pass 2 (WRITE = true) repeats the walk and writes the bytes.
+// table; pass 2 (WRITE = true) repeats the walk and writes the bytes. A lane
+// walks one column, or two (j and j + 64) when D exceeds 64, so that a
+// segment's lane group stays inside one wavefront.
 #pragma once
 
 #include "spz_device.h"
@@ -35,23 +37,28 @@ __global__ __launch_bounds__(kThreads) void k_encode(const typename Elem<W>::T *
     constexpr uint32_t HB = W == 8 ? 3 : 4;
     constexpr uint32_t WB = W / 8;
     __shared__ uint32_t hring[512];
-    __shared__ uint32_t pbuf[COLMAJOR ? 1 : kThreads * W / 4];
+    __shared__ uint32_t pbuf[COLMAJOR ? 1 : 2 * kThreads * W / 4];
 
-    const uint32_t Dp = 1u << g.dp_log2;
+    const uint32_t Dp = 1u << g.dp_log2;          // padded columns of a segment
+    const uint32_t lg = min(g.dp_log2, 6u);
+    const uint32_t Dl = 1u << lg;                 // lanes of a segment
     const uint32_t gid = blockIdx.x * kThreads + threadIdx.x;
-    const uint32_t seg = gid >> g.dp_log2;
-    const uint32_t j = gid & (Dp - 1);
+    const uint32_t seg = gid >> lg;
+    const uint32_t j = gid & (Dl - 1);
     if (seg >= g.nseg) return;  // whole lane groups leave together
-    const bool col = j < g.D;
     const uint32_t D = g.D;
+    constexpr uint32_t CPL = 2;                   // column slots of a lane: j and j + 64
+    const uint32_t ncs = D > Dl ? 2u : 1u;
+    bool col[CPL];
+    for (uint32_t c = 0; c < CPL; ++c) col[c] = c < ncs && j + 64 * c < D;
 
     const uint64_t row0 = (uint64_t)seg * g.S;
     const uint32_t nr = (uint32_t)min((uint64_t)g.S, g.rows - row0);
     const uint32_t nblk = nr >> 3, tail = nr & 7u;
-    const T *xs = src + row0 * D + (col ? j : 0);
+    const T *xs = src + row0 * D + j;
 
     // write state
-    const uint32_t gw = threadIdx.x >> g.dp_log2;  // lane group within the workgroup
+    const uint32_t gw = threadIdx.x >> lg;         // lane group within the workgroup
     const uint32_t RW = ring_words(Dp);
     uint32_t *ring = hring + gw * RW;
     uint32_t *pay = pbuf + (COLMAJOR ? 0 : gw * (Dp * W / 4));
@@ -67,9 +74,9 @@ __global__ __launch_bounds__(kThreads) void k_encode(const typename Elem<W>::T *
         base = g.data_start + ld_u64_aligned(dst + 64 + 8ull * seg);
         seg_size = seg_info[2 * seg];
         nrec_total = seg_info[2 * seg + 1];
-        for (uint32_t k = j; k < RW; k += Dp) ring[k] = 0;
+        for (uint32_t k = j; k < RW; k += Dl) ring[k] = 0;
         if (!COLMAJOR)
-            for (uint32_t k = j; k < Dp * W / 4; k += Dp) pay[k] = 0;
+            for (uint32_t k = j; k < Dp * W / 4; k += Dl) pay[k] = 0;
         if (j == 0) {
             if (base + 4 <= g.cap) *reinterpret_cast<uint32_t *>(dst + base) = nrec_total;
             else overflow = true;
@@ -77,12 +84,12 @@ __global__ __launch_bounds__(kThreads) void k_encode(const typename Elem<W>::T *
     }
 
     uint32_t nrec = 0, payload = 0, run = 0;
-    uint32_t prev = 0;
-    int32_t delta = 0, acc = 0;
+    uint32_t prev[CPL] = {0, 0};
+    int32_t delta[CPL] = {0, 0}, acc[CPL] = {0, 0};
 
-    // Emit one record: header code of this lane's column, payload bytes.
-    auto emit = [&](uint32_t code, bool is_rle, uint32_t count, const uint32_t *z, uint32_t width, uint32_t off,
-                    uint32_t wsum) {
+    // Emit one record: header codes of this lane's columns, payload bytes.
+    auto emit = [&](const uint32_t *codes, bool is_rle, uint32_t count, const uint32_t (*zz)[8], const uint32_t *widths,
+                    const uint32_t *offs, uint32_t wsum) {
         if (grp_left == 0) {
             uint32_t cnt = g.G ? min(g.G, nrec_total - r) : nrec_total;
             hstart = cursor;
@@ -91,8 +98,10 @@ __global__ __launch_bounds__(kThreads) void k_encode(const typename Elem<W>::T *
             hflushed = 0;
             grp_left = cnt;
         }
-        if (code != 0) {
-            uint32_t p = hbit + j * HB;
+        for (uint32_t c = 0; c < ncs; ++c) {
+            const uint32_t code = codes[c];
+            if (code == 0) continue;
+            uint32_t p = hbit + (j + 64 * c) * HB;
             uint32_t w0 = (p >> 5) & (RW - 1), s = p & 31u;
             atomicOr(&ring[w0], code << s);
             if (s + HB > 32) atomicOr(&ring[(w0 + 1) & (RW - 1)], code >> (32 - s));
@@ -106,6 +115,8 @@ __global__ __launch_bounds__(kThreads) void k_encode(const typename Elem<W>::T *
             cursor += 2;
         } else if (COLMAJOR) {
             // column j: its 8 values, width bits each, LSB first = width bytes
+            const uint32_t *z = zz[0];
+            const uint32_t width = widths[0], off = offs[0];
             uint64_t lo = 0, hi = 0;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
@@ -125,16 +136,18 @@ __global__ __launch_bounds__(kThreads) void k_encode(const typename Elem<W>::T *
         } else {
             // row-major: row i = fields of all columns, padded to a byte
             const uint32_t R = (wsum + 7) >> 3;
-            if (width != 0) {
+            for (uint32_t c = 0; c < ncs; ++c) {
+                const uint32_t width = widths[c], off = offs[c];
+                if (width == 0) continue;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     uint32_t p = (uint32_t)i * 8 * R + off;
                     uint32_t w0 = p >> 5, s = p & 31u;
-                    atomicOr(&pay[w0], z[i] << s);
-                    if (s + width > 32) atomicOr(&pay[w0 + 1], z[i] >> (32 - s));
+                    atomicOr(&pay[w0], zz[c][i] << s);
+                    if (s + width > 32) atomicOr(&pay[w0 + 1], zz[c][i] >> (32 - s));
                 }
             }
-            for (uint32_t k = j; k < 8 * R; k += Dp) {
+            for (uint32_t k = j; k < 8 * R; k += Dl) {
                 uint32_t sh = (k & 3u) * 8;
                 uint32_t old = atomicAnd(&pay[k >> 2], ~(0xFFu << sh));
                 st(base + cursor + k, (old >> sh) & 0xFFu);
@@ -144,7 +157,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(const typename Elem<W>::T *
         grp_left--;
         r++;
         uint32_t complete = grp_left == 0 ? (hbit + 7) >> 3 : hbit >> 3;
-        for (uint32_t k = hflushed + j; k < complete; k += Dp) {
+        for (uint32_t k = hflushed + j; k < complete; k += Dl) {
             uint32_t wi = (k >> 2) & (RW - 1), sh = (k & 3u) * 8;
             uint32_t old = atomicAnd(&ring[wi], ~(0xFFu << sh));
             st(base + hstart + k, (old >> sh) & 0xFFu);
@@ -152,33 +165,38 @@ __global__ __launch_bounds__(kThreads) void k_encode(const typename Elem<W>::T *
         hflushed = complete;
     };
 
+    const uint32_t zcodes[CPL] = {0, 0}, zw[CPL] = {0, 0};
     for (uint32_t b = 0; b < nblk; ++b) {
-        const int32_t alpha = FIRE ? (acc >> g.sh) : 0;
-        int32_t grad = 0;
-        uint32_t z[8];
-        uint32_t orz = 0;
+        uint32_t z[CPL][8], code[CPL] = {0, 0}, width[CPL] = {0, 0}, off[CPL] = {0, 0};
+        uint32_t wsum = 0;
+        for (uint32_t c = 0; c < ncs; ++c) {
+            const int32_t alpha = FIRE ? (acc[c] >> g.sh) : 0;
+            int32_t grad = 0;
+            uint32_t orz = 0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const uint32_t x = col ? (uint32_t)xs[(uint64_t)(8 * b + i) * D] : 0u;
-            int32_t pred = (int32_t)prev;
-            if (FIRE) pred += __mul24(alpha, delta) >> W;
-            const int32_t e = sext<W>((int32_t)x - pred);
-            if (FIRE && (i & 1)) grad += __mul24(sgn(e), delta);
-            delta = sext<W>((int32_t)x - (int32_t)prev);
-            prev = x;
-            z[i] = zigzag(e);
-            orz |= z[i];
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t x = col[c] ? (uint32_t)xs[(uint64_t)(8 * b + i) * D + 64 * c] : 0u;
+                int32_t pred = (int32_t)prev[c];
+                if (FIRE) pred += __mul24(alpha, delta[c]) >> W;
+                const int32_t e = sext<W>((int32_t)x - pred);
+                if (FIRE && (i & 1)) grad += __mul24(sgn(e), delta[c]);
+                delta[c] = sext<W>((int32_t)x - (int32_t)prev[c]);
+                prev[c] = x;
+                z[c][i] = zigzag(e);
+                orz |= z[c][i];
+            }
+            if (FIRE) acc[c] = min(max(acc[c] + grad, g.acc_lo), g.acc_hi);
+            code[c] = min(bitlen(orz), (uint32_t)W - 1);
+            width[c] = code[c] < (uint32_t)W - 1 ? code[c] : (uint32_t)W;
+            // columns j + 64 follow all of the first 64 in the row
+            const uint32_t incl = group_incl_sum(width[c], Dl, j);
+            off[c] = wsum + incl - width[c];
+            wsum += group_last(incl, Dl);
         }
-        if (FIRE) acc = min(max(acc + grad, g.acc_lo), g.acc_hi);
-        const uint32_t nbits = bitlen(orz);
-        const uint32_t code = min(nbits, (uint32_t)W - 1);
-        const uint32_t width = code < (uint32_t)W - 1 ? code : (uint32_t)W;
-        const uint32_t incl = group_incl_sum(width, Dp, j);
-        const uint32_t wsum = group_last(incl, Dp);
         if (wsum == 0) {
             run++;
             if (run == kRleMax) {
-                if (WRITE) emit(0, true, run, z, 0, 0, 0);
+                if (WRITE) emit(zcodes, true, run, z, zw, zw, 0);
                 nrec++;
                 payload += 2;
                 run = 0;
@@ -186,18 +204,18 @@ __global__ __launch_bounds__(kThreads) void k_encode(const typename Elem<W>::T *
             continue;
         }
         if (run > 0) {
-            if (WRITE) emit(0, true, run, z, 0, 0, 0);
+            if (WRITE) emit(zcodes, true, run, z, zw, zw, 0);
             nrec++;
             payload += 2;
             run = 0;
         }
-        if (WRITE) emit(code, false, 0, z, width, incl - width, wsum);
+        if (WRITE) emit(code, false, 0, z, width, off, wsum);
         nrec++;
         payload += COLMAJOR ? wsum : 8 * ((wsum + 7) >> 3);
     }
     if (run > 0) {
-        uint32_t z0[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (WRITE) emit(0, true, run, z0, 0, 0, 0);
+        const uint32_t z0[CPL][8] = {};
+        if (WRITE) emit(zcodes, true, run, z0, zw, zw, 0);
         nrec++;
         payload += 2;
     }
@@ -212,16 +230,17 @@ __global__ __launch_bounds__(kThreads) void k_encode(const typename Elem<W>::T *
         return;
     }
     // raw tail rows (last segment only), then zero padding to 16 bytes
-    if (col) {
+    for (uint32_t c = 0; c < ncs; ++c) {
+        if (!col[c]) continue;
         for (uint32_t t = 0; t < tail; ++t) {
-            uint32_t x = (uint32_t)xs[(uint64_t)(8 * nblk + t) * D];
-            uint32_t pos = cursor + (t * D + j) * WB;
+            uint32_t x = (uint32_t)xs[(uint64_t)(8 * nblk + t) * D + 64 * c];
+            uint32_t pos = cursor + (t * D + j + 64 * c) * WB;
             for (uint32_t q = 0; q < WB; ++q) st(base + pos + q, (x >> (8 * q)) & 0xFFu);
         }
     }
     cursor += tail_bytes;
     const uint32_t end = (cursor + 15) & ~15u;
-    for (uint32_t k = cursor + j; k < end; k += Dp) st(base + k, 0);
+    for (uint32_t k = cursor + j; k < end; k += Dl) st(base + k, 0);
     if (j == 0 && (end != seg_size || r != nrec_total)) overflow = true;
     if (overflow && status) atomicOr(status, 2);
 }

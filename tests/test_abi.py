@@ -91,7 +91,7 @@ def test_argument_validation_without_gpu(lib):
     fake = 1 << 20  # never dereferenced
     assert spz.sprintz_compress(fake, 100, 0, 4, p, fake, 1 << 20, fake, fake, 1 << 10, 0, 0) == spz.SPZ_EINVAL
     assert spz.sprintz_compress(fake, 100, 3, 9, p, fake, 1 << 20, fake, fake, 1 << 10, 0, 0) == spz.SPZ_EINVAL
-    assert spz.sprintz_compress(fake, 100, 65, 4, p, fake, 1 << 20, fake, fake, 1 << 10, 0, 0) == spz.SPZ_EUNSUPPORTED
+    assert spz.sprintz_compress(fake, 100, 129, 4, p, fake, 1 << 20, fake, fake, 1 << 10, 0, 0) == spz.SPZ_EUNSUPPORTED
     assert spz.sprintz_compress(fake, 100, 3, 4, p, fake, 10, fake, fake, 1 << 10, 0, 0) == spz.SPZ_ENOSPC
     assert spz.sprintz_compress(fake, 100, 3, 4, p, fake, 1 << 20, fake, fake, 0, 0, 0) == spz.SPZ_ENOSPC
     assert spz.sprintz_compress(fake, 100, 3, 4, p, fake + 8, 1 << 20, fake, fake, 1 << 10, 0, 0) == spz.SPZ_EINVAL

@@ -235,3 +235,16 @@ def test_both_encoders_give_the_oracle_bytes(f):
         ref = oracle.compress(x, f, S)
         assert _gpu_compress_ws(x, f, S, spz.sprintz_workspace_size) == ref
         assert _gpu_compress_ws(x, f, S, spz.sprintz_workspace_size_min) == ref
+
+
+@pytest.mark.parametrize("D", [65, 72, 80, 128])
+def test_more_than_64_columns(D):
+    # the paper's speed experiments go to 80 columns: lanes take columns j
+    # and j + 64; both widths and forecasters, ragged rows, grouped headers
+    for dt, f, G in ((np.uint16, "fire", 0), (np.int8, "delta", 0), (np.uint8, "fire", 2), (np.int16, "delta", 1)):
+        x = datagen.ar2_uint16(20000 + 5, D, sigma=30, seed=D).astype(dt)
+        _check(x, f, 1024, G, label=f"D={D}")
+    x = datagen.uniform(4096 + 7, D, np.uint16, seed=D + 1)
+    _check(x, "fire", 512, label=f"uniform D={D}")
+    for rows in (0, 1, 7, 8, 9):
+        _check(datagen.uniform(rows, D, np.uint8, seed=rows), "fire", 64, label=f"D={D} rows={rows}")
