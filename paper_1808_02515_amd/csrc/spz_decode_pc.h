@@ -441,7 +441,7 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
                     // E = e * 2^w, taken straight from the packed field
                     int32_t E;
                     if (WB == 2) E = (i & 1) ? (int32_t)(ev[i >> 1] & 0xFFFF0000u) : (int32_t)(ev[i >> 1] << 16);
-                    else E = __builtin_amdgcn_sbfe((int32_t)ev[i >> 2], 8 * (i & 3), 8) << 8;
+                    else E = (int32_t)((uint32_t)__builtin_amdgcn_sbfe((int32_t)ev[i >> 2], 8 * (i & 3), 8) << 8);
                     if (FIRE) {
                         // wrapping sum: only bits [w, 2w) are used
                         const int32_t tt = (int32_t)((uint32_t)E + (uint32_t)__mul24(alpha, delta));
@@ -461,7 +461,8 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
             // ---- output: each segment's rows of this chunk ---------------------
             const uint32_t bic = c * CB < c_nb ? min((uint32_t)CB, c_nb - c * CB) : 0u;
             const uint32_t valid = bic * 8 * D * WB;
-            uint8_t *const gp = c_dst + (size_t)c * CB * 8 * D * WB;
+            // (lanes without a column chain have no rows: valid is 0 there)
+            uint8_t *const gp = c_on ? c_dst + (size_t)c * CB * 8 * D * WB : c_dst;
 #pragma unroll
             for (uint32_t u = 0; u < G::UPL; ++u) {
                 const uint32_t lo = 16 * (cj + u * D);
