@@ -345,15 +345,19 @@ template <int W, bool FIRE, int D> __device__ __forceinline__ void es_encode_gro
                 }
                 wave_sync();
                 // ---- block lanes: (segment, block); records of the chunk -----------
+                // every lane takes part in the scans (lanes past the wave's
+                // slots form groups of their own and write nothing)
 #pragma unroll
                 for (uint32_t rr = 0; rr < (WSLOT + 63) / 64; ++rr) {
-                    const uint32_t q = lane + 64 * rr;
-                    if (q < WSLOT) {
-                        const uint32_t bb = q % CB;
+                    const uint32_t qr = lane + 64 * rr;
+                    const bool qa = qr < WSLOT;
+                    const uint32_t q = qa ? qr : 0u;
+                    {
+                        const uint32_t bb = qr % CB;
                         const uint32_t ss = wseg(q / CB);
                         const EsSeg sq = SEG[ss];
                         const u32x4 bv = BLK[wave][q];
-                        const bool nz = bv.w != 0 && bv.x != 0;
+                        const bool nz = qa && bv.w != 0 && bv.x != 0;
                         const uint32_t qbic = c * CB < sq.nblk ? min(CB, sq.nblk - c * CB) : 0u;
                         // last nonzero block up to this one, 1-based (0 = none)
                         const uint32_t lastin = es_incl_max<CB>(nz ? bb + 1 : 0u, bb);
@@ -377,8 +381,8 @@ template <int W, bool FIRE, int D> __device__ __forceinline__ void es_encode_gro
                         res.z = 0;
                         res.w = 0;
                         wave_sync();
-                        BLK[wave][q] = res;
-                        if (bb == 0 && ss < nsw) {
+                        if (qa) BLK[wave][q] = res;
+                        if (qa && bb == 0 && ss < nsw) {
                             EsSeg &ns = SEG[ss];
                             ns.r0 = sq.r;
                             ns.cursor0 = sq.cursor;
@@ -388,8 +392,6 @@ template <int W, bool FIRE, int D> __device__ __forceinline__ void es_encode_gro
                                 ns.run = lastall == 0 ? sq.run + qbic : qbic - lastall;
                             }
                         }
-                    } else {
-                        wave_sync();
                     }
                 }
                 wave_sync();
