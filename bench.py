@@ -30,9 +30,15 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
 
 
 def kernel_source_hash() -> str:
+    """sha256 (first 16 hex digits) of the device code: the kernel headers
+    csrc/spz_*.h. The host runtime (sprintz.hip: validation, plans, stream
+    order) does not change the bytes a kernel launch moves."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1808_02515_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_1808_02515_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_1808_02515_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if not (f.startswith("spz_") and f.endswith(".h")):
+            continue
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
