@@ -667,6 +667,81 @@ hipError_t launch_decode_any(const void *d_src, const spz_info *info, const spz:
 // share one compiled form; a plan holds one work list per class.
 constexpr int kClasses = 2 * 2 * 16;   // w in {8, 16} x forecaster x D in 1..16
 int class_of(uint32_t w, bool fire, uint32_t D) { return ((w == 16) * 2 + fire) * 16 + (int)(D - 1); }
+
+// Concurrent class launches. A batch's class kernels are independent; run
+// one after another, a class whose few long workgroups leave most of the GPU
+// idle (small D: many segments per workgroup, few workgroups) keeps the
+// others waiting. They go instead to up to kLanes streams: the caller's and
+// kLanes - 1 side streams of the device (default priority, created once per
+// device and kept), forked from and joined back into the caller's stream
+// with events, so the call stays stream-ordered and can be captured in a
+// HIP graph. Calls on different caller streams that share the side streams
+// are ordered on them but stay correct.
+constexpr int kLanes = 4;
+hipError_t side_streams(hipStream_t *out) {
+    static std::mutex mu;
+    static std::map<int, std::vector<hipStream_t>> pool;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    std::vector<hipStream_t> &v = pool[dev];
+    while (v.size() < kLanes - 1) {
+        hipStream_t s = nullptr;
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        v.push_back(s);
+    }
+    for (int k = 0; k < kLanes - 1; ++k) out[k] = v[k];
+    return hipSuccess;
+}
+
+// Fork/join events of one plan (created with the plan).
+struct Lanes {
+    hipEvent_t fork = nullptr, join[kLanes - 1] = {};
+    bool ok = false;
+    hipError_t create() {
+        hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        for (int k = 0; k < kLanes - 1 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&join[k], hipEventDisableTiming);
+        ok = e == hipSuccess;
+        return e;
+    }
+    void destroy() {
+        if (fork) (void)hipEventDestroy(fork);
+        for (int k = 0; k < kLanes - 1; ++k)
+            if (join[k]) (void)hipEventDestroy(join[k]);
+        fork = nullptr;
+        ok = false;
+    }
+    // streams[0] = the caller's; launches go to streams[i % used]
+    hipError_t begin(hipStream_t stream, int used, hipStream_t *streams) const {
+        streams[0] = stream;
+        if (used <= 1) return hipSuccess;
+        hipError_t e = side_streams(streams + 1);
+        if (e == hipSuccess) e = hipEventRecord(fork, stream);
+        for (int k = 1; k < used && e == hipSuccess; ++k) e = hipStreamWaitEvent(streams[k], fork, 0);
+        return e;
+    }
+    hipError_t end(int used, hipStream_t *streams) const {
+        hipError_t e = hipSuccess;
+        for (int k = 1; k < used && e == hipSuccess; ++k) {
+            e = hipEventRecord(join[k - 1], streams[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(streams[0], join[k - 1], 0);
+        }
+        return e;
+    }
+};
+
+// Classes with work, longest first (samples, with a per-record share that
+// weighs small D): the longest runs on the caller's stream, the rest spread
+// over the side streams.
+template <typename Cost> int lane_order(const uint32_t *ngroups, Cost cost, int *order) {
+    int n = 0;
+    for (int c = 0; c < kClasses; ++c)
+        if (ngroups[c]) order[n++] = c;
+    std::stable_sort(order, order + n, [&](int x, int y) { return cost(x) > cost(y); });
+    return n;
+}
 uint32_t class_D(int c) { return (uint32_t)(c % 16) + 1; }
 uint32_t class_w(int c) { return (c / 32) ? 16 : 8; }
 bool class_fire(int c) { return (c / 16) % 2; }
@@ -717,6 +792,8 @@ struct spz_batch {
     uint32_t ngroups[kClasses];
     uint32_t grid[kClasses];
     uint32_t *queues;                              // one work counter per class
+    double work[kClasses];                         // launch order weight per class
+    Lanes lanes;
     // streams that take the single-container path
     struct Fallback { const void *src; void *dst; spz_info info; spz::Geom g; uint32_t index; };
     Fallback *fallback;
@@ -873,6 +950,9 @@ spz_status build_plan(const spz_batch_item *items, const spz_info *infos, uint32
 #undef SPZ_CAPD
 #undef SPZ_CAP
         b->grid[c] = std::min(b->ngroups[c], cap);
+        double wk = 0;
+        for (uint32_t gi = 0; gi < gs[c].size(); ++gi) wk += (double)gs[c][gi];
+        b->work[c] = wk * spz::pc_spw(class_D(c), spz::kPcProducers, spz::kPcConsumers) * (class_D(c) + 4.0);
     }
     b->nfallback = (uint32_t)fb.size();
     b->fallback = nullptr;
@@ -910,7 +990,8 @@ spz_status sprintz_batch_create(const spz_batch_item *items, const spz_info *inf
     st = build_plan(items, infos, n, b, (uint8_t *)b->dmem);
     if (st == SPZ_OK && hipMemcpy(b->dmem, b->host.data(), b->host.size(), hipMemcpyHostToDevice) != hipSuccess)
         st = SPZ_EHIP;
-    if (st != SPZ_OK) { (void)hipFree(b->dmem); delete[] b->fallback; delete b; return st; }
+    if (st == SPZ_OK && b->lanes.create() != hipSuccess) st = SPZ_EHIP;
+    if (st != SPZ_OK) { b->lanes.destroy(); (void)hipFree(b->dmem); delete[] b->fallback; delete b; return st; }
     *out = b;
     return SPZ_OK;
 }
@@ -926,7 +1007,8 @@ spz_status sprintz_batch_create_in(const spz_batch_item *items, const spz_info *
     if (st == SPZ_OK &&
         hipMemcpyAsync(d_ws, b->host.data(), b->host.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
         st = SPZ_EHIP;
-    if (st != SPZ_OK) { delete[] b->fallback; delete b; return st; }
+    if (st == SPZ_OK && b->lanes.create() != hipSuccess) st = SPZ_EHIP;
+    if (st != SPZ_OK) { b->lanes.destroy(); delete[] b->fallback; delete b; return st; }
     b->dmem = d_ws;
     b->owns = false;
     *out = b;
@@ -937,13 +1019,19 @@ spz_status sprintz_batch_create_in(const spz_batch_item *items, const spz_info *
 spz_status sprintz_batch_decompress(const spz_batch *b, int32_t *d_status, hipStream_t stream) {
     if (!b) return SPZ_EINVAL;
     hipLaunchKernelGGL(spz::k_zero_u32, dim3(1), dim3(64), 0, stream, b->queues, (uint32_t)kClasses);
-    for (int c = 0; c < kClasses; ++c) {
-        if (!b->ngroups[c]) continue;
+    int order[kClasses];
+    const int ncls = lane_order(b->ngroups, [&](int c) { return b->work[c]; }, order);
+    const int used = std::min(ncls, kLanes);
+    hipStream_t ls[kLanes];
+    if (b->lanes.begin(stream, used, ls) != hipSuccess) return SPZ_EHIP;
+    for (int oi = 0; oi < ncls; ++oi) {
+        const int c = order[oi];
+        hipStream_t cs = ls[oi % used];
         hipError_t e = hipSuccess;
 #define SPZ_BL(W_, F_, D_)                                                                                      \
     if (class_w(c) == W_ && class_fire(c) == F_ && class_D(c) == D_)                                            \
         e = launch_batch_class<W_, F_, D_>(b->streams, b->entries[c], b->group_s[c], b->ngroups[c], b->queues + c, \
-                                           d_status, b->grid[c], stream);
+                                           d_status, b->grid[c], cs);
 #define SPZ_BLD(W_, F_)                                                                                   \
     SPZ_BL(W_, F_, 1) SPZ_BL(W_, F_, 2) SPZ_BL(W_, F_, 3) SPZ_BL(W_, F_, 4) SPZ_BL(W_, F_, 5) SPZ_BL(W_, F_, 6)         \
     SPZ_BL(W_, F_, 7) SPZ_BL(W_, F_, 8) SPZ_BL(W_, F_, 9) SPZ_BL(W_, F_, 10) SPZ_BL(W_, F_, 11)                     \
@@ -953,6 +1041,7 @@ spz_status sprintz_batch_decompress(const spz_batch *b, int32_t *d_status, hipSt
 #undef SPZ_BL
         if (e != hipSuccess) return SPZ_EHIP;
     }
+    if (b->lanes.end(used, ls) != hipSuccess) return SPZ_EHIP;
     for (uint32_t k = 0; k < b->nfallback; ++k) {
         const spz_batch::Fallback &f = b->fallback[k];
         if (launch_decode_any(f.src, &f.info, f.g, f.dst, d_status ? d_status + f.index : nullptr, stream) != hipSuccess)
@@ -963,6 +1052,7 @@ spz_status sprintz_batch_decompress(const spz_batch *b, int32_t *d_status, hipSt
 
 void sprintz_batch_destroy(spz_batch *b) {
     if (!b) return;
+    b->lanes.destroy();
     if (b->owns) (void)hipFree(b->dmem);
     delete[] b->fallback;
     delete b;
@@ -985,6 +1075,9 @@ struct spz_cbatch {
     uint32_t ncgroups;
     struct Fallback { spz_compress_item item; void *ws; size_t ws_size; uint32_t index; };
     std::vector<Fallback> fallback;                // series the batched kernels do not take
+    double work[kClasses];                         // launch order weight per class
+    Lanes lanes;
+    ~spz_cbatch() { lanes.destroy(); }
 };
 
 namespace {
@@ -1039,6 +1132,7 @@ bool cbatch_takes(const spz_compress_item &it) {
 // own workspace.
 spz_status build_cplan(const spz_compress_item *items, uint32_t n, spz_cbatch *b, uint8_t *base, size_t *total) {
     b->n = n;
+    for (int c = 0; c < kClasses; ++c) b->work[c] = 0;
     std::vector<int> cls(n, -1);
     uint32_t nb = 0;
     for (uint32_t i = 0; i < n; ++i) {
@@ -1061,6 +1155,7 @@ spz_status build_cplan(const spz_compress_item *items, uint32_t n, spz_cbatch *b
         const uint32_t nseg = (uint32_t)num_segments(items[i].rows, S);
         const uint32_t spw = 64 / spz::pc_pow2(D);
         for (uint32_t s0 = 0; s0 < nseg; s0 += spw) grp[cls[i]].push_back(make_uint2(k, s0));
+        b->work[cls[i]] += (double)items[i].rows * (D + 4.0);
         const uint64_t units = sp_slot_stride(S, D, w) / 16;
         const uint32_t K = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(256, 2048 / units));
         for (uint32_t s0 = 0; s0 < nseg; s0 += K) cg.push_back(make_uint4(k, s0, K, 0));
@@ -1158,6 +1253,7 @@ spz_status sprintz_compress_batch_create_in(const spz_compress_item *items, uint
     if (st == SPZ_OK && !b->host.empty() &&
         hipMemcpyAsync(d_ws, b->host.data(), b->host.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
         st = SPZ_EHIP;
+    if (st == SPZ_OK && b->lanes.create() != hipSuccess) st = SPZ_EHIP;
     if (st != SPZ_OK) { delete b; return st; }
     *out = b;
     return SPZ_OK;
@@ -1166,12 +1262,18 @@ spz_status sprintz_compress_batch_create_in(const spz_compress_item *items, uint
 spz_status sprintz_compress_batch(const spz_cbatch *b, int32_t *d_status, hipStream_t stream) {
     if (!b) return SPZ_EINVAL;
     hipLaunchKernelGGL(spz::k_zero_u32, dim3(1), dim3(64), 0, stream, b->queues, (uint32_t)kClasses);
-    for (int c = 0; c < kClasses; ++c) {
-        if (!b->ngroups[c]) continue;
+    int order[kClasses];
+    const int ncls = lane_order(b->ngroups, [&](int c) { return b->work[c]; }, order);
+    const int used = std::min(ncls, kLanes);
+    hipStream_t ls[kLanes];
+    if (b->lanes.begin(stream, used, ls) != hipSuccess) return SPZ_EHIP;
+    for (int oi = 0; oi < ncls; ++oi) {
+        const int c = order[oi];
+        hipStream_t cs = ls[oi % used];
 #define SPZ_CBL(W_, F_, D_)                                                                                      \
     if (class_w(c) == W_ && class_fire(c) == F_ && class_D(c) == D_)                                             \
         hipLaunchKernelGGL((spz::k_encode_sp_batch<W_, F_, D_>), dim3(b->grid[c]), dim3(spz::es_threads(D_)), 0, \
-                           stream, b->streams, b->groups[c], b->ngroups[c], b->queues + c);
+                           cs, b->streams, b->groups[c], b->ngroups[c], b->queues + c);
 #define SPZ_CBLD(W_, F_)                                                                                  \
     SPZ_CBL(W_, F_, 1) SPZ_CBL(W_, F_, 2) SPZ_CBL(W_, F_, 3) SPZ_CBL(W_, F_, 4) SPZ_CBL(W_, F_, 5)          \
     SPZ_CBL(W_, F_, 6) SPZ_CBL(W_, F_, 7) SPZ_CBL(W_, F_, 8) SPZ_CBL(W_, F_, 9) SPZ_CBL(W_, F_, 10)         \
@@ -1181,6 +1283,7 @@ spz_status sprintz_compress_batch(const spz_cbatch *b, int32_t *d_status, hipStr
 #undef SPZ_CBLD
 #undef SPZ_CBL
     }
+    if (b->lanes.end(used, ls) != hipSuccess) return SPZ_EHIP;
     if (b->nscan) hipLaunchKernelGGL(spz::k_enc_scan_batch, dim3(b->nscan), dim3(256), 0, stream, b->streams,
                                      b->scan_list, d_status);
     if (b->ncgroups) hipLaunchKernelGGL(spz::k_enc_compact_batch, dim3(b->ncgroups), dim3(256), 0, stream, b->streams,
