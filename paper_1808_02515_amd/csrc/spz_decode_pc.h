@@ -15,10 +15,14 @@
 //                                 each record covers
 //                         stage   16-byte loads of chunk t+1's header and
 //                                 payload windows into registers
-//                         unpack  lanes = (segment, block, column): 8 fields
-//                                 each, aligned two-dword LDS reads and a
-//                                 funnel shift; unzigzag; the errors e go to
-//                                 an LDS buffer per column chain
+//                         unpack  an aligned two-dword LDS read and a
+//                                 funnel shift give 32 bits = 32/w fields:
+//                                 lanes = (segment, block, 32/w adjacent
+//                                 columns) for row-major payloads, one read
+//                                 per row; (segment, block, column) for
+//                                 column-major ones, one read per 32/w rows;
+//                                 unzigzag; the errors e go to an LDS buffer
+//                                 per column chain
 //   consumer (chunk t-1)  lane = column chain. For FIRE
 //                              t     = e * 2^w + alpha * delta   (v_mad_i32_i24)
 //                              delta = bits [w, 2w) of t, signed   (v_bfe_i32)
@@ -119,7 +123,10 @@ template <int W, int D, int CB, int NP, int NC> struct PcGeom {
     static constexpr uint32_t PPASS = (PAIRS + 63) / 64;           // parse passes
     static constexpr uint32_t SUNITS = SPP * NU;                   // staged units per producer
     static constexpr uint32_t SPASS = (SUNITS + 63) / 64;
-    static constexpr uint32_t ITEMS = SPP * CB * DP;               // unpack items per producer
+    static constexpr bool ROW = D * W > 32;                        // row-major payloads (reading R13)
+    static constexpr uint32_t GF = 32 / W;                         // fields of one 32-bit read
+    static constexpr uint32_t IL = ROW ? DP / GF : DP;             // unpack lanes per (segment, block)
+    static constexpr uint32_t ITEMS = SPP * CB * IL;               // unpack items per producer
     static constexpr uint32_t IPASS = (ITEMS + 63) / 64;
     static constexpr uint32_t ZSTR = CB * 8 * WB + 16;             // error buffer bytes per chain
     static constexpr bool WIDE = D * WB >= 16;
@@ -189,6 +196,7 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
     constexpr uint32_t ZSTR = G::ZSTR, OSEG = G::OSEG;
     constexpr bool ROW = D * W > 32;   // row-major payloads (reading R13)
     static_assert(SPP * NP == SPW && SPP >= 1 && SPP <= 64 && CB <= 16 && G::DP <= 16, "geometry");
+    static_assert(!G::ROW || G::IL >= 2, "row-major items hold whole column groups");
 
     // One LDS arena, staging windows first: field addresses then need no base.
     constexpr uint32_t O_ZB = SPW * NU * 16;                       // [segment][header window | payload window]
@@ -337,75 +345,100 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
             wave_sync();
             // ---- stage the next chunk's windows -----------------------------
             if (c + 1 < nchunks) stage_issue();
-            // ---- unpack: lanes = (segment, block, column < DP) ---------------
-            // All LDS reads of the chunk's items are issued in three batches
-            // (block map, records, fields) so that their latency is paid
-            // three times per chunk rather than three times per item.
+            // ---- unpack ------------------------------------------------------
+            // One aligned two-dword LDS read and a funnel shift give 32
+            // payload bits: GF = 32 / W fields at once. Row-major payloads
+            // (fields of one row side by side): lanes = (segment, block, GF
+            // adjacent columns), one read per row. Column-major payloads (a
+            // column's 8 fields side by side): lanes = (segment, block,
+            // column), one read per GF rows. All LDS reads of the chunk's
+            // items are issued in three batches (block map, records, fields)
+            // so that their latency is paid three times per chunk rather than
+            // three times per item.
             uint8_t *const zbuf = zb + (c & 1) * G::CHAINS * ZSTR;
-            constexpr uint32_t IP = G::IPASS;
+            constexpr uint32_t IP = G::IPASS, IL = G::IL, GF = G::GF;
+            constexpr uint32_t NRD = ROW ? 8 : 8 / GF;   // reads per item
             uint32_t kk[IP];
 #pragma unroll
             for (uint32_t ip = 0; ip < IP; ++ip) {
                 const uint32_t it = lane + 64 * ip;
-                const uint32_t b = (it / G::DP) % CB, s = ps0 + min(it / (G::DP * CB), SPP - 1);
+                const uint32_t b = (it / IL) % CB, s = ps0 + min(it / (IL * CB), SPP - 1);
                 kk[ip] = BM[s * CB + b];
             }
             u32x4 rr[IP];
 #pragma unroll
             for (uint32_t ip = 0; ip < IP; ++ip) {
                 const uint32_t it = lane + 64 * ip;
-                const uint32_t s = ps0 + min(it / (G::DP * CB), SPP - 1);
+                const uint32_t s = ps0 + min(it / (IL * CB), SPP - 1);
                 rr[ip] = REC[s * CB + (kk[ip] & (CB - 1))];
             }
-            uint32_t fw[IP][8][2], wd[IP];
+            // widths of the item's columns (0 past D), the bit offset of each
+            // field group and the 32 bits read there
+            uint32_t wdt[IP][ROW ? GF : 1], fw[IP][NRD];
 #pragma unroll
             for (uint32_t ip = 0; ip < IP; ++ip) {
                 const uint32_t it = lane + 64 * ip;
-                const uint32_t j = it % G::DP;
-                const bool nz = it < G::ITEMS && j < (uint32_t)D && kk[ip] != kPcZero;
+                const uint32_t q = it % IL;                       // column group (ROW) or column
+                const bool nz = it < G::ITEMS && kk[ip] != kPcZero;
                 const u32x4 rec = rr[ip];
-                const uint32_t bp = j * HB;
-                const uint32_t code = !nz ? 0u
-                                      : bp + HB <= 32 ? __builtin_amdgcn_ubfe(rec.x, bp, HB)
-                                      : bp >= 32      ? __builtin_amdgcn_ubfe(rec.y, bp - 32, HB)
-                                                      : __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(rec.y, rec.x, bp), 0, HB);
-                const uint32_t width = code + ((code + 1) >> HB);   // code w-1 stands for width w
-                const uint32_t off = pc_incl<G::DP>(width, j) - width;
-                const uint32_t p0 = nz ? rec.z + (ROW ? off : 8 * off) : 0u;
-                const uint32_t step = !nz ? 0u : ROW ? rec.w : width;
-                wd[ip] = width;
+                constexpr uint32_t NCOL = ROW ? GF : 1;          // columns of the item
+                constexpr uint32_t CBITS = NCOL * HB;            // their header code bits
+                const uint32_t bp = q * CBITS;
+                const uint32_t cw = bp >= 32 ? rec.y >> (bp - 32) : __builtin_amdgcn_alignbit(rec.y, rec.x, bp);
+                uint32_t sum = 0;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const uint32_t p = p0 + (uint32_t)i * step;
-                    const uint32_t *q = stgw + (p >> 5);
-                    fw[ip][i][0] = q[0];
-                    fw[ip][i][1] = q[1];
-                    fw[ip][i][0] = __builtin_amdgcn_alignbit(fw[ip][i][1], fw[ip][i][0], p);
+                for (uint32_t g = 0; g < NCOL; ++g) {
+                    const uint32_t code = __builtin_amdgcn_ubfe(cw, g * HB, HB);
+                    const uint32_t width = nz && q * NCOL + g < (uint32_t)D ? code + ((code + 1) >> HB) : 0u;   // code w-1 stands for width w
+                    wdt[ip][ROW ? g : 0] = width;
+                    sum += width;
+                }
+                const uint32_t off = pc_incl<IL>(sum, q) - sum;  // bits before the item's first column
+                // ROW: field (i, first column) at rec.z + off + i * (row bits);
+                // column-major: fields GF*k .. GF*k+GF-1 at rec.z + 8*off + GF*k*width
+                const uint32_t p0 = nz ? rec.z + (ROW ? off : 8 * off) : 0u;
+                const uint32_t step = !nz ? 0u : ROW ? rec.w : GF * sum;
+#pragma unroll
+                for (uint32_t r = 0; r < NRD; ++r) {
+                    const uint32_t p = p0 + r * step;
+                    const uint32_t *qd = stgw + (p >> 5);
+                    fw[ip][r] = __builtin_amdgcn_alignbit(qd[1], qd[0], p);
                 }
             }
 #pragma unroll
             for (uint32_t ip = 0; ip < IP; ++ip) {
                 const uint32_t it = lane + 64 * ip;
-                const uint32_t j = it % G::DP, b = (it / G::DP) % CB, s = ps0 + min(it / (G::DP * CB), SPP - 1);
-                uint32_t z[8];
+                const uint32_t q = it % IL, b = (it / IL) % CB, s = ps0 + min(it / (IL * CB), SPP - 1);
+                constexpr uint32_t NCOL = ROW ? GF : 1;
+                uint32_t o = 0;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) z[i] = __builtin_amdgcn_ubfe(fw[ip][i][0], 0, wd[ip]);
-                if (it < G::ITEMS && j < (uint32_t)D) {
-                    uint8_t *zp = zbuf + (s * D + j) * ZSTR + b * 8 * WB;
-                    // zigzag fields packed 2 (or 4) per dword, then unzigzagged lane-wise:
-                    // e = (z >> 1) ^ -(z & 1) in every 16-bit (8-bit) lane
-                    if (WB == 2) {
-                        u32x4 v;
-                        v.x = unzigzag16x2(z[0] | (z[1] << 16));
-                        v.y = unzigzag16x2(z[2] | (z[3] << 16));
-                        v.z = unzigzag16x2(z[4] | (z[5] << 16));
-                        v.w = unzigzag16x2(z[6] | (z[7] << 16));
-                        *reinterpret_cast<u32x4 *>(zp) = v;
-                    } else {
-                        uint2 v;
-                        v.x = unzigzag8x4(z[0] | (z[1] << 8) | (z[2] << 16) | (z[3] << 24));
-                        v.y = unzigzag8x4(z[4] | (z[5] << 8) | (z[6] << 16) | (z[7] << 24));
-                        *reinterpret_cast<uint2 *>(zp) = v;
+                for (uint32_t g = 0; g < NCOL; ++g) {
+                    const uint32_t j = q * NCOL + g;
+                    const uint32_t w = wdt[ip][ROW ? g : 0];
+                    // the column's 8 zigzag codes
+                    uint32_t z[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        z[i] = ROW ? __builtin_amdgcn_ubfe(fw[ip][i], o, w)
+                                   : __builtin_amdgcn_ubfe(fw[ip][i / GF], (i % GF) * w, w);
+                    o += w;
+                    if (it < G::ITEMS && j < (uint32_t)D) {
+                        uint8_t *zp = zbuf + (s * D + j) * ZSTR + b * 8 * WB;
+                        // zigzag codes packed 2 (or 4) per dword, then unzigzagged
+                        // lane-wise: e = (z >> 1) ^ -(z & 1) in every 16-bit (8-bit) lane
+                        if (WB == 2) {
+                            u32x4 v;
+                            v.x = unzigzag16x2(z[0] | (z[1] << 16));
+                            v.y = unzigzag16x2(z[2] | (z[3] << 16));
+                            v.z = unzigzag16x2(z[4] | (z[5] << 16));
+                            v.w = unzigzag16x2(z[6] | (z[7] << 16));
+                            *reinterpret_cast<u32x4 *>(zp) = v;
+                        } else {
+                            uint2 v;
+                            v.x = unzigzag8x4(z[0] | (z[1] << 8) | (z[2] << 16) | (z[3] << 24));
+                            v.y = unzigzag8x4(z[4] | (z[5] << 8) | (z[6] << 16) | (z[7] << 24));
+                            *reinterpret_cast<uint2 *>(zp) = v;
+                        }
                     }
                 }
             }

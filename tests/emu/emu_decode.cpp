@@ -59,7 +59,10 @@ template <int W, bool FIRE>
 static bool dispatch_pc(uint32_t D, const uint8_t *src, const spz::Geom &g, uint8_t *dst, int32_t *st, uint32_t *nb) {
     switch (D) {
         case 1: run_pc<W, FIRE, 1>(src, g, dst, st, nb); return true;
+        case 2: run_pc<W, FIRE, 2>(src, g, dst, st, nb); return true;
         case 3: run_pc<W, FIRE, 3>(src, g, dst, st, nb); return true;
+        case 4: run_pc<W, FIRE, 4>(src, g, dst, st, nb); return true;
+        case 5: run_pc<W, FIRE, 5>(src, g, dst, st, nb); return true;
         case 8: run_pc<W, FIRE, 8>(src, g, dst, st, nb); return true;
         case 16: run_pc<W, FIRE, 16>(src, g, dst, st, nb); return true;
         default: return false;

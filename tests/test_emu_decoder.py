@@ -70,7 +70,7 @@ def test_one_segment_walk_in_bounds(harness, tmp_path, f):
 def test_corpus_decodes_exactly_in_bounds(harness, tmp_path):
     rng = np.random.default_rng(0)
     for k in range(40):
-        D = int(rng.choice([1, 3, 8, 16, 20, 80]))
+        D = int(rng.choice([1, 2, 3, 4, 5, 8, 16, 20, 80]))
         rows = int(rng.choice([0, 1, 7, 8, 9, 100, 1000, 3000]))
         dt = [np.int8, np.uint16][k % 2]
         x = datagen.ar2_uint16(rows, D, sigma=float(rng.uniform(1, 100)), seed=k).astype(dt)
