@@ -82,6 +82,50 @@ template <int N> __device__ __forceinline__ uint32_t pc_total(uint32_t v) {
     return v;
 }
 
+// Sum of the widths that D header codes of HB bits (LSB first in hi:lo)
+// stand for: code c is width c, except the largest code 2^HB - 1, which is
+// width w = c + 1 (Section 4.3: a width of w - 1 never occurs). Summed with
+// byte sums (HB = 4) or bit-plane popcounts (HB = 3) instead of one code at
+// a time.
+__host__ __device__ constexpr uint64_t pc_plane(int D, int HB, int k) {
+    uint64_t m = 0;
+    for (int j = 0; j < D; ++j) m |= 1ull << (HB * j + k);
+    return m;
+}
+template <int D, int HB> __device__ __forceinline__ uint32_t pc_width_sum(uint32_t lo, uint32_t hi) {
+    static_assert(D * HB <= 64 && (HB == 3 || HB == 4), "header codes");
+    if constexpr (HB == 4) {
+        auto part = [](uint32_t x) -> uint32_t {
+            const uint32_t s = (x & 0x0F0F0F0Fu) + ((x >> 4) & 0x0F0F0F0Fu);   // nibble pairs, per byte
+            const uint32_t top = x & (x >> 1) & (x >> 2) & (x >> 3) & 0x11111111u;   // codes 15
+            return __builtin_amdgcn_sad_u8(s, 0u, 0u) + (uint32_t)__builtin_popcount(top);
+        };
+        constexpr uint64_t M = pc_plane(D, 4, 0) * 15u;
+        uint32_t t = part(lo & (uint32_t)M);
+        if constexpr (D > 8) t += part(hi & (uint32_t)(M >> 32));
+        return t;
+    } else {
+        constexpr uint64_t M0 = pc_plane(D, 3, 0), M1 = pc_plane(D, 3, 1), M2 = pc_plane(D, 3, 2);
+        auto pc2 = [&](uint64_t m) -> uint32_t {
+            return (uint32_t)__builtin_popcount(lo & (uint32_t)m) +
+                   (D * 3 > 32 ? (uint32_t)__builtin_popcount(hi & (uint32_t)(m >> 32)) : 0u);
+        };
+        uint32_t t = pc2(M0) + 2 * pc2(M1) + 4 * pc2(M2);
+        // codes 7: all three bits set
+        const uint32_t lo1 = __builtin_amdgcn_alignbit(hi, lo, 1), lo2 = __builtin_amdgcn_alignbit(hi, lo, 2);
+        t += (uint32_t)__builtin_popcount(lo & lo1 & lo2 & (uint32_t)M0);
+        if constexpr (D * 3 > 32) t += (uint32_t)__builtin_popcount(hi & (hi >> 1) & (hi >> 2) & (uint32_t)(M0 >> 32));
+        return t;
+    }
+}
+
+// a * (low w bits of d, sign-extended), one v_mul_i32_i24 with an SDWA
+// operand (a within 24 bits).
+template <int W> __device__ __forceinline__ int32_t pc_mul_sext(int32_t a, int32_t d) {
+    if constexpr (W == 16) return __mul24(a, (int32_t)(int16_t)d);
+    else return mul24_sext8(a, d);
+}
+
 // Unzigzag of two 16-bit (four 8-bit) fields of a dword at once.
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t unzigzag16x2(uint32_t zz) {
@@ -296,15 +340,7 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
                 const uint32_t *hw = stgw + s * NU * 4;
                 const uint32_t cw_lo = lds_bits32(hw, hp);
                 const uint32_t cw_hi = D * HB > 32 ? lds_bits32(hw, hp + 32) : 0u;
-                uint32_t total = 0;
-#pragma unroll
-                for (uint32_t jj = 0; jj < (uint32_t)D; ++jj) {
-                    const uint32_t bp = jj * HB;
-                    const uint32_t code = bp + HB <= 32 ? __builtin_amdgcn_ubfe(cw_lo, bp, HB)
-                                          : bp >= 32    ? __builtin_amdgcn_ubfe(cw_hi, bp - 32, HB)
-                                                        : __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(cw_hi, cw_lo, bp), 0, HB);
-                    total += code + ((code + 1) >> HB);   // code w-1 stands for width w
-                }
+                const uint32_t total = pc_width_sum<D, HB>(cw_lo, cw_hi);
                 const bool zero = total == 0;
                 const uint32_t size = !valid ? 0u : zero ? 2u : (ROW ? 8 * ((total + 7) >> 3) : total);
                 const uint32_t poff = sg.cursor + pc_incl<CB>(size, k) - size;   // payload byte of candidate k
@@ -471,18 +507,24 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
                 int32_t grad = 0;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    // E = e * 2^w, taken straight from the packed field
-                    int32_t E;
-                    if (WB == 2) E = (i & 1) ? (int32_t)(ev[i >> 1] & 0xFFFF0000u) : (int32_t)(ev[i >> 1] << 16);
-                    else E = (int32_t)((uint32_t)__builtin_amdgcn_sbfe((int32_t)ev[i >> 2], 8 * (i & 3), 8) << 8);
+                    // e: the packed field read as a signed w-bit word (the
+                    // compiler takes it as a sign-extended SDWA operand)
+                    const uint32_t word = ev[WB == 2 ? i >> 1 : i >> 2];
+                    const int32_t e = WB == 2 ? ((i & 1) ? (int32_t)(int16_t)(word >> 16) : (int32_t)(int16_t)word)
+                                              : (int32_t)(int8_t)(word >> (8 * (i & 3)));
                     if (FIRE) {
-                        // wrapping sum: only bits [w, 2w) are used
-                        const int32_t tt = (int32_t)((uint32_t)E + (uint32_t)__mul24(alpha, delta));
-                        if (i & 1) grad += __mul24(sgn_med3(E), delta);
-                        delta = __builtin_amdgcn_sbfe(tt, (uint32_t)W, (uint32_t)W);
+                        // delta = e + floor(alpha * delta_prev / 2^w) modulo 2^w.
+                        // delta is kept unreduced: only its low w bits are
+                        // read, sign-extended, and |alpha * delta_prev| < 2^31
+                        // (2^15 for w = 8), so bits [w, 32) of the product
+                        // are the floor (wrapping add of e * 2^w gives the same
+                        // bits [w, 2w)).
+                        const int32_t p = pc_mul_sext<W>(alpha, delta);
+                        if (i & 1) grad += pc_mul_sext<W>(sgn_med3(e), delta);
+                        delta = (W == 16 ? (p >> 16) : (int32_t)(int8_t)(p >> 8)) + e;
                         x += (uint32_t)delta;
                     } else {
-                        x += (uint32_t)(E >> W);
+                        x += (uint32_t)e;
                     }
                     const uint32_t o = obase + (uint32_t)((8 * b + i) * D * WB);
                     if (WB == 1) outb[o] = (uint8_t)x;

@@ -1,6 +1,6 @@
 // Hardware-specific operations of the gfx950 Sprintz kernels: bounded
-// buffer resources, plain global accessors, the wavefront hand-off point and
-// the sign in one v_med3_i32. Included by spz_device.h through the include
+// buffer resources, plain global accessors, the wavefront hand-off point, the
+// sign in one v_med3_i32 and a 24-bit product with a sign-extended byte. Included by spz_device.h through the include
 // path, so that a host build of the kernel source can supply checked
 // versions of exactly these operations.
 #pragma once
@@ -16,6 +16,17 @@ __device__ __forceinline__ int32_t sgn_med3(int32_t e) {
     int32_t r;
     asm("v_med3_i32 %0, %1, -1, 1" : "=v"(r) : "v"(e));
     return r;
+}
+
+// a * (low byte of d, sign-extended) in one v_mul_i32_i24 with an SDWA
+// operand (a within 24 bits). Written out because the compiler widens the
+// 8-bit form into a 32-bit multiply.
+__device__ __forceinline__ int32_t mul24_sext8(int32_t a, int32_t d) {
+    int32_t p;
+    asm("v_mul_i32_i24_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+        : "=v"(p)
+        : "v"(a), "v"(d));
+    return p;
 }
 
 // Bounded global memory: a buffer resource covers [base, base + bytes) and the

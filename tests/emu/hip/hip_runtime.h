@@ -87,6 +87,15 @@ inline int emu_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mas
     return (int)emu::wave_op(emu::OP_DPP, (uint32_t)src, ctrl, 64);
 }
 inline uint32_t emu_readfirstlane(uint32_t v) { return emu::wave_op(emu::OP_FIRST, v, 0, 64); }
+inline uint32_t emu_sad_u8(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t t = c;
+    for (int k = 0; k < 4; ++k) {
+        const int x = (int)((a >> (8 * k)) & 255u), y = (int)((b >> (8 * k)) & 255u);
+        t += (uint32_t)(x > y ? x - y : y - x);
+    }
+    return t;
+}
+#define __builtin_amdgcn_sad_u8 emu_sad_u8
 #define __builtin_amdgcn_ubfe emu_ubfe
 #define __builtin_amdgcn_sbfe emu_sbfe
 #define __builtin_amdgcn_alignbit emu_alignbit

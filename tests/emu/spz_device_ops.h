@@ -33,6 +33,12 @@ inline bool inside(const void *p, size_t n, bool write) {
 namespace spz {
 
 __device__ __forceinline__ int32_t sgn_med3(int32_t e) { return e < -1 ? -1 : e > 1 ? 1 : e; }
+// v_mul_i32_i24 of a (low 24 bits, signed) and the sign-extended low byte of
+// d; the low 32 bits of the product
+__device__ __forceinline__ int32_t mul24_sext8(int32_t a, int32_t d) {
+    const int64_t a24 = (int64_t)(int32_t)((uint32_t)a << 8) >> 8;
+    return (int32_t)(uint32_t)(uint64_t)(a24 * (int64_t)(int8_t)d);
+}
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
