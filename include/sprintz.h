@@ -243,10 +243,15 @@ spz_status sprintz_batch_create_in(const spz_batch_item *items, const spz_info *
 
 /* Enqueue the decoding of every item of the plan on `stream`: a tiny kernel
  * resets the per-class queues, then one launch per nonempty class, then the
- * fallback streams. d_status: n int32 device words (zero on entry, or NULL);
- * corrupt data in item i sets bit 1 of d_status[i]. Allocates nothing and
- * never synchronizes, so the call can be captured into a HIP graph. Calls
- * that overlap on one plan race on its queues. */
+ * fallback streams. The class launches run concurrently on up to four
+ * streams: `stream` and three side streams of the device that the library
+ * creates once (default priority) and keeps, forked from `stream` and joined
+ * back into it with the plan's events, so all work stays ordered after
+ * earlier work on `stream` and before later work on it, also under graph
+ * capture. d_status: n int32 device words (zero on entry, or NULL); corrupt
+ * data in item i sets bit 1 of d_status[i]. Allocates nothing and never
+ * synchronizes, so the call can be captured into a HIP graph. Calls that
+ * overlap on one plan race on its queues and events. */
 spz_status sprintz_batch_decompress(const spz_batch *b, int32_t *d_status, hipStream_t stream);
 
 /* Free a plan (NULL is ignored). The caller makes sure no enqueued work uses it. */
@@ -291,11 +296,14 @@ size_t sprintz_compress_batch_workspace_size(const spz_compress_item *items, uin
 spz_status sprintz_compress_batch_create_in(const spz_compress_item *items, uint32_t n, void *d_ws, size_t ws_size,
                                             hipStream_t stream, spz_cbatch **out);
 
-/* Enqueue the compression of every item on `stream`. d_status: n int32
- * device words (zero on entry, or NULL); a size problem of item i sets bit 2
- * of d_status[i]. Allocates nothing and never synchronizes, so the call can
- * be captured into a HIP graph. Calls that overlap on one plan race on its
- * queues and workspace. */
+/* Enqueue the compression of every item on `stream`. The class launches of
+ * the batched encoder run concurrently on `stream` and the device's side
+ * streams, joined back into `stream` before the offset scan (as for
+ * sprintz_batch_decompress). d_status: n int32 device words (zero on entry,
+ * or NULL); a size problem of item i sets bit 2 of d_status[i]. Allocates
+ * nothing and never synchronizes, so the call can be captured into a HIP
+ * graph. Calls that overlap on one plan race on its queues, events and
+ * workspace. */
 spz_status sprintz_compress_batch(const spz_cbatch *b, int32_t *d_status, hipStream_t stream);
 
 /* Free a plan (NULL is ignored); its device tables are the caller's memory. */
