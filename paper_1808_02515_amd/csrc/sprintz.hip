@@ -203,8 +203,8 @@ hipError_t launch_decode(const void *src, const spz::Geom &g, void *dst, int32_t
 #define SPZ_PC(D_)                                                                                        \
     case D_:                                                                                              \
         hipLaunchKernelGGL((spz::k_decode_pc<W, FIRE, D_, spz::kPcProducers, spz::kPcConsumers>), dim3(grid), \
-                           dim3(64 * (spz::kPcProducers + spz::kPcConsumers)), 0, stream, (const uint8_t *)src, \
-                           g, (T *)dst, status);                                                          \
+                           dim3(spz::pc_single_threads(D_, spz::kPcProducers, spz::kPcConsumers)), 0, stream,  \
+                           (const uint8_t *)src, g, (T *)dst, status);                                    \
         break;
             SPZ_PC(1) SPZ_PC(2) SPZ_PC(3) SPZ_PC(4) SPZ_PC(5) SPZ_PC(6) SPZ_PC(7) SPZ_PC(8)
             SPZ_PC(9) SPZ_PC(10) SPZ_PC(11) SPZ_PC(12) SPZ_PC(13) SPZ_PC(14) SPZ_PC(15) SPZ_PC(16)
@@ -750,7 +750,7 @@ template <int W, bool FIRE, int D>
 hipError_t launch_batch_class(const spz::PcStream *streams, const uint64_t *entries, const uint32_t *group_s,
                               uint32_t ngroups, uint32_t *queue, int32_t *status, uint32_t grid, hipStream_t stream) {
     hipLaunchKernelGGL((spz::k_decode_pc_batch<W, FIRE, D, spz::kPcProducers, spz::kPcConsumers>), dim3(grid),
-                       dim3(64 * (spz::kPcProducers + spz::kPcConsumers)), 0, stream, streams, entries, group_s,
+                       dim3(spz::pc_threads(spz::kPcProducers, spz::kPcConsumers)), 0, stream, streams, entries, group_s,
                        ngroups, queue, status);
     return hipGetLastError();
 }
@@ -771,7 +771,7 @@ uint32_t batch_grid_cap() {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &per_cu, (const void *)spz::k_decode_pc_batch<W, FIRE, D, spz::kPcProducers, spz::kPcConsumers>,
-            64 * (spz::kPcProducers + spz::kPcConsumers), 0) != hipSuccess)
+            spz::pc_threads(spz::kPcProducers, spz::kPcConsumers), 0) != hipSuccess)
         return 1;
     const uint32_t cap = (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)(cus > 0 ? cus : 1);
     std::lock_guard<std::mutex> lk(mu);

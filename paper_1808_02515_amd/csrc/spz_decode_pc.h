@@ -1,43 +1,48 @@
-// Producer/consumer Sprintz decoder for gfx950 (header group = whole
-// segment, D up to 16).
+// Pipelined Sprintz decoder for gfx950 (header group = whole segment, D up
+// to 16).
 //
 // Paper: Algorithm 2 (decodeBlock) with the forecasters of Section 4.2. Of
 // the decoding work only the forecaster recurrence is serial (Section 5.4
 // names the dependence of each prediction on the previous sample as the
-// limit). A workgroup therefore splits into NP producer wavefronts and NC
-// consumer wavefronts (64 column chains each) that work on consecutive chunks
-// at the same time:
+// limit). A workgroup holds the segments of 64 column chains and splits into
+// a three-stage pipeline of wavefronts over chunks of 8 blocks, one barrier
+// per step:
 //
-//   producers (chunk t)   parse   lanes = (segment, candidate record k of the
-//                                 chunk): the record's header codes give its
-//                                 width sum and byte size; scans over k give
-//                                 payload offsets, run counts and the blocks
-//                                 each record covers
-//                         stage   16-byte loads of chunk t+1's header and
-//                                 payload windows into registers
-//                         unpack  an aligned two-dword LDS read and a
-//                                 funnel shift give 32 bits = 32/w fields:
-//                                 lanes = (segment, block, 32/w adjacent
-//                                 columns) for row-major payloads, one read
-//                                 per row; (segment, block, column) for
-//                                 column-major ones, one read per 32/w rows;
-//                                 unzigzag; the errors e go to an LDS buffer
-//                                 per column chain
-//   consumer (chunk t-1)  lane = column chain. For FIRE
-//                              t     = e * 2^w + alpha * delta   (v_mad_i32_i24)
-//                              delta = bits [w, 2w) of t, signed   (v_bfe_i32)
+//   parser (chunk t)       stage   the loads of chunk t, issued a step
+//                                  earlier, go from registers to LDS
+//                          parse   lanes = (segment, candidate record k of
+//                                  the chunk): the record's header codes give
+//                                  its width sum and byte size; scans over k
+//                                  give payload offsets, run counts and the
+//                                  blocks each record covers
+//                          issue   16-byte loads of chunk t+1's header and
+//                                  payload windows (their bases come from the
+//                                  parse), in flight over the rest of the step
+//   NP unpackers (t-1)     an aligned two-dword LDS read and a funnel shift
+//                          give 32 bits = 32/w fields: lanes = (segment,
+//                          block, 32/w adjacent columns) for row-major
+//                          payloads, one read per row; (segment, block,
+//                          column) for column-major ones, one read per 32/w
+//                          rows; unzigzag; the errors e go to an LDS buffer
+//                          per column chain
+//   consumer (chunk t-2)   lane = column chain. For FIRE
+//                              delta = e + floor(alpha * delta_prev / 2^w)   (mod 2^w)
 //                              x    += delta
-//                         which equals x_hat + e with x_hat = x_{i-1} +
-//                         floor(alpha * delta / 2^w) modulo 2^w; sgn(e) *
-//                         delta_{i-1} is summed on odd rows and the
-//                         accumulator saturates once per block (practical
-//                         FIRE, Section 4.2.2). Samples go to an LDS image of
-//                         the chunk's rows, which leaves with 16-byte stores.
+//                          with e and the product's high bits as sign-extended
+//                          SDWA operands (one multiply and one add on the
+//                          serial chain); sgn(e) * delta_prev is summed on odd
+//                          rows and the accumulator saturates once per block
+//                          (practical FIRE, Section 4.2.2). Samples go to an
+//                          LDS image of the chunk's rows, which leaves with
+//                          16-byte stores.
+//
+// Staging windows, records and error buffers are double buffered by chunk
+// parity, so each stage reads what the one before wrote a step earlier.
 //
 // A block inside a run of zero blocks decodes as a block whose errors are
 // all 0 (reading R9: the prediction alone; sgn(0) = 0 leaves the FIRE
-// accumulator as it is), so runs need no separate path. One barrier per chunk
-// hands the error buffers over (double buffered). Every LDS access is aligned.
+// accumulator as it is), so runs need no separate path. Every LDS access is
+// aligned.
 //
 // Global accesses are plain loads and stores, each behind an explicit range
 // check:
@@ -56,8 +61,24 @@
 namespace spz {
 
 constexpr int kPcChunkBlocks = 8;
-constexpr int kPcProducers = 2;      // producer wavefronts per workgroup
+constexpr int kPcProducers = 2;      // unpacking wavefronts per workgroup
 constexpr int kPcConsumers = 1;      // consumer wavefronts per workgroup
+__host__ __device__ constexpr uint32_t pc_threads(uint32_t NP, uint32_t NC) { return 64 * (NP + NC); }
+__host__ __device__ constexpr uint32_t pc_spw(uint32_t D, uint32_t NP, uint32_t NC);
+// The single-container kernel takes the pipelined form (a parser wavefront
+// besides NP unpacking and NC consumer wavefronts) when one parser pass covers
+// the workgroup's (segment, candidate record) pairs (D >= 7); with more passes
+// the parser becomes the longest stage (measured: D = 1, 2, 3, 6 decode
+// slower, D = 4 level). The batched kernel keeps the producer/consumer form
+// (NP producers, NC consumers) at every D: its smaller LDS and register
+// footprint keeps four workgroups on a CU where the pipelined form fits three,
+// and batched throughput follows the number of consumer chains in flight.
+__host__ __device__ constexpr bool pc_pipe(uint32_t D) {
+    return pc_spw(D, kPcProducers, kPcConsumers) * kPcChunkBlocks <= 64;
+}
+__host__ __device__ constexpr uint32_t pc_single_threads(uint32_t D, uint32_t NP, uint32_t NC) {
+    return pc_pipe(D) ? 64 * (1 + NP + NC) : 64 * (NP + NC);
+}
 constexpr uint32_t kPcZero = 0xFFu;  // block map entry of a zero (run) block
 
 template <int CTRL> __device__ __forceinline__ uint32_t pc_dpp(uint32_t v) {
@@ -163,10 +184,14 @@ template <int W, int D, int CB, int NP, int NC> struct PcGeom {
     static constexpr uint32_t HU = (CB * D * HB / 8 + 28 + 15) / 16;   // header window units
     static constexpr uint32_t PU = (CB * MAXREC + 24 + 15) / 16;       // payload window units
     static constexpr uint32_t NU = HU + PU;
+    // producer/consumer form: each producer parses and stages its own segments
     static constexpr uint32_t PAIRS = SPP * CB;                    // (segment, candidate) per producer
     static constexpr uint32_t PPASS = (PAIRS + 63) / 64;           // parse passes
-    static constexpr uint32_t SUNITS = SPP * NU;                   // staged units per producer
-    static constexpr uint32_t SPASS = (SUNITS + 63) / 64;
+    // pipelined form: one parser wave for all segments
+    static constexpr uint32_t PPAIRS = SPW * CB;                   // (segment, candidate) of the parser
+    static constexpr uint32_t PPPASS = (PPAIRS + 63) / 64;         // its parse passes
+    static constexpr uint32_t LPS = 64 / SPW;                      // its staging lanes per segment
+    static constexpr uint32_t SP2 = (NU + LPS - 1) / LPS;          // its staged units per lane
     static constexpr bool ROW = D * W > 32;                        // row-major payloads (reading R13)
     static constexpr uint32_t GF = 32 / W;                         // fields of one 32-bit read
     static constexpr uint32_t IL = ROW ? DP / GF : DP;             // unpack lanes per (segment, block)
@@ -230,8 +255,11 @@ __device__ __forceinline__ void pc_seg_init(PcSeg &sg, const uint8_t *src, uint6
     sg.pbase = sg.cursor & ~15u;
 }
 
-// Decodes the segments whose state the producers put in SEG (nchunks chunks of
-// kPcChunkBlocks blocks). Called by all threads of the workgroup.
+// Producer/consumer form: NP producer wavefronts parse, stage and unpack
+// their own segments' chunk t while the consumer runs the recurrence of
+// chunk t-1; one barrier per chunk. Decodes the segments whose state the
+// producers put in SEG (nchunks chunks of kPcChunkBlocks blocks). Called by
+// all threads of the workgroup.
 template <int W, bool FIRE, int D, int NP, int NC, typename Init>
 __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int32_t *__restrict__ status) {
     constexpr int CB = kPcChunkBlocks;
@@ -577,9 +605,371 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
     }
 }
 
+// Pipelined form: decodes the segments whose state the parser puts in SEG
+// (nchunks chunks of kPcChunkBlocks blocks). Called by all threads of the
+// workgroup. The
+// wavefronts form a three-stage pipeline over the chunks, one barrier per
+// step: at step t the parser (wave 0) stores chunk t's staged windows, parses
+// chunk t and issues the loads of chunk t+1's windows; the NP unpacking waves
+// unpack chunk t-1; the consumer runs the recurrence of chunk t-2. Staging
+// windows, records and error buffers are double buffered by chunk parity.
+template <int W, bool FIRE, int D, int NP, int NC, typename Init>
+__device__ __forceinline__ void pc_decode_group_pipe(uint32_t nchunks, Init init, int32_t *__restrict__ status) {
+    constexpr int CB = kPcChunkBlocks;
+    using G = PcGeom<W, D, CB, NP, NC>;
+    constexpr uint32_t HB = G::HB, WB = G::WB, SPW = G::SPW, SPP = G::SPP, HU = G::HU, NU = G::NU;
+    constexpr uint32_t ZSTR = G::ZSTR, OSEG = G::OSEG;
+    constexpr bool ROW = D * W > 32;   // row-major payloads (reading R13)
+    static_assert(SPP * NP == SPW && SPP >= 1 && SPP <= 64 && SPW <= 64 && CB <= 16 && G::DP <= 16, "geometry");
+    static_assert(!G::ROW || G::IL >= 2, "row-major items hold whole column groups");
+
+    // One LDS arena, staging windows first: field addresses then need no base.
+    constexpr uint32_t SLOT = SPW * NU * 16;                       // one chunk's windows
+    constexpr uint32_t O_ZB = 2 * SLOT;                            // [parity][segment][header | payload window]
+    constexpr uint32_t O_OUT = O_ZB + 2 * G::CHAINS * ZSTR;        // [parity][chain] errors of a chunk
+    // [segment] output rows of a chunk, plus a discard image for consumer
+    // lanes without a column chain (D not dividing the wavefront)
+    constexpr uint32_t NOUT = G::USED < G::CHAINS ? SPW + 1 : SPW;
+    constexpr uint32_t O_REC = (O_OUT + NOUT * OSEG + 15) & ~15u;
+    constexpr uint32_t O_BM = O_REC + 2 * SPW * CB * 16;           // [parity][segment][candidate]: codes lo, hi, payload bit, bits per row
+    constexpr uint32_t O_SEG = (O_BM + 2 * SPW * CB * 4 + 15) & ~15u;  // [parity][segment][block]: candidate or kPcZero
+    constexpr uint32_t O_END = O_SEG + SPW * (uint32_t)sizeof(PcSeg);
+    __shared__ u32x4 ARENA[O_END / 16];
+    u32x4 *const STG = ARENA;
+    u32x4 *const ZB4 = reinterpret_cast<u32x4 *>(reinterpret_cast<uint8_t *>(ARENA) + O_ZB);
+    uint32_t *const OUTW = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(ARENA) + O_OUT);
+    u32x4 *const REC = reinterpret_cast<u32x4 *>(reinterpret_cast<uint8_t *>(ARENA) + O_REC);
+    uint32_t *const BM = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(ARENA) + O_BM);
+    PcSeg *const SEG = reinterpret_cast<PcSeg *>(reinterpret_cast<uint8_t *>(ARENA) + O_SEG);
+    static_assert(O_END % 16 == 0 && sizeof(PcSeg) % 16 == 0, "arena layout");
+    const uint32_t *const stgw = reinterpret_cast<const uint32_t *>(STG);
+    uint8_t *const zb = reinterpret_cast<uint8_t *>(ZB4);
+    uint8_t *const outb = reinterpret_cast<uint8_t *>(OUTW);
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t wave = tid >> 6, lane = tid & 63;
+    const bool parser = wave == 0;
+    const bool consumer = wave > NP;
+    const bool unpacker = !parser && !consumer;
+    const uint32_t ps0 = unpacker ? (wave - 1) * SPP : 0u;   // an unpacking wave's first segment
+
+    // ---- parser: segment state and the first chunk's windows ------------------
+    // staging: each lane moves units of one segment (64 / SPW lanes per segment),
+    // so it reads that segment's state once per chunk
+    constexpr uint32_t LPS = G::LPS, SP2 = G::SP2;
+    const bool st_on = lane < LPS * SPW;
+    const uint32_t st_s = min(lane / LPS, SPW - 1), st_k = lane % LPS;
+    u32x4 reg[SP2];
+    auto stage_issue = [&]() {
+        const PcSeg &sg = SEG[st_s];
+        const uint8_t *const src = sg.src;
+        const uint32_t ext = sg.ok ? sg.ext : 0u, hbase = sg.hbase, pbase = sg.pbase;
+#pragma unroll
+        for (uint32_t t = 0; t < SP2; ++t) {
+            const uint32_t k = st_k + LPS * t;
+            const uint32_t off = k < HU ? hbase + 16 * k : pbase + 16 * (k - HU);
+            u32x4 v = {0u, 0u, 0u, 0u};
+            // only whole 16-byte units inside the segment (its extent is a multiple of 16)
+            if (st_on && k < NU && off + 16 <= ext) v = gld128(src + off);
+            reg[t] = v;
+        }
+    };
+    auto stage_commit = [&](uint32_t c) {
+        u32x4 *const slot = STG + (c & 1) * (SLOT / 16);
+#pragma unroll
+        for (uint32_t t = 0; t < SP2; ++t) {
+            const uint32_t k = st_k + LPS * t;
+            if (st_on && k < NU) slot[st_s * NU + k] = reg[t];
+        }
+    };
+    if (parser) {
+        if (lane < SPW) init(SEG[lane], lane);
+        wave_sync();
+        stage_issue();
+    }
+    __syncthreads();
+
+    // ---- consumer state: one column chain per lane ----------------------------
+    const uint32_t chain = consumer ? (wave - NP - 1) * 64 + lane : 0u;
+    const bool c_on = consumer && chain < G::USED;
+    const uint32_t cs = c_on ? chain / D : SPW, cj = c_on ? chain % D : 0u;
+    uint32_t x = 0;
+    int32_t delta = 0, acc = 0;
+    uint32_t c_sh = 0, c_nb = 0;
+    int32_t c_lo = 0, c_hi = 0;
+    uint8_t *c_dst = nullptr;
+    if (c_on) {
+        const PcSeg &q = SEG[cs];
+        c_sh = q.sh; c_lo = q.acc_lo; c_hi = q.acc_hi; c_dst = q.dst; c_nb = q.nrow >> 3;
+    }
+
+    for (uint32_t t = 0; t < nchunks + 2; ++t) {
+        if (parser && t < nchunks) {
+            const uint32_t c = t;
+            stage_commit(c);
+            wave_sync();
+            // ---- parse: lanes = (segment, candidate record) -----------------
+            const uint32_t *const slotw = stgw + (c & 1) * (SLOT / 4);
+#pragma unroll
+            for (uint32_t pp = 0; pp < G::PPPASS; ++pp) {
+                const uint32_t pr = lane + 64 * pp;
+                const uint32_t sl = pr / CB, k = pr % CB;
+                const uint32_t s = min(sl, SPW - 1);
+                const bool here = pr < G::PPAIRS;
+                const PcSeg sg = SEG[s];   // one read of the chunk's state
+                const uint32_t nbk = sg.nrow >> 3;
+                const uint32_t bic = c * CB < nbk ? min((uint32_t)CB, nbk - c * CB) : 0u;
+                const uint32_t rr = sg.r + k;
+                const bool valid = here && sg.ok && rr < sg.nrec;
+                // header codes of record rr (D * HB <= 64 bits)
+                const uint32_t hp = 32 + rr * D * HB - 8 * sg.hbase;   // bit in the header window
+                const uint32_t *hw = slotw + s * NU * 4;
+                const uint32_t cw_lo = lds_bits32(hw, hp);
+                const uint32_t cw_hi = D * HB > 32 ? lds_bits32(hw, hp + 32) : 0u;
+                const uint32_t total = pc_width_sum<D, HB>(cw_lo, cw_hi);
+                const bool zero = total == 0;
+                const uint32_t size = !valid ? 0u : zero ? 2u : (ROW ? 8 * ((total + 7) >> 3) : total);
+                const uint32_t poff = sg.cursor + pc_incl<CB>(size, k) - size;   // payload byte of candidate k
+                const uint32_t pb = poff - sg.pbase;                               // byte in the payload window
+                const uint32_t *pw = hw + HU * 4;
+                const uint32_t cnt = lds_bits32(pw, 8 * pb) & 0xFFFFu;
+                const uint32_t nb = !valid ? 0u : zero ? cnt : 1u;
+                const bool badk = valid && zero && cnt == 0;
+                const uint32_t start = sg.rle_rem + pc_incl<CB>(nb, k) - nb;     // first block it covers
+                const bool used = valid && start < bic;
+                uint32_t *const bm = BM + (c & 1) * SPW * CB;
+                if (here) bm[s * CB + k] = kPcZero;
+                wave_sync();
+                if (used && !zero) {
+                    u32x4 rec;
+                    rec.x = cw_lo;
+                    rec.y = cw_hi;
+                    // payload bit in the staging array (this chunk's parity slot)
+                    rec.z = 8 * ((c & 1) * SLOT + (s * NU + HU) * 16 + pb);
+                    rec.w = ROW ? 8 * ((total + 7) >> 3) : 0u;
+                    REC[(c & 1) * SPW * CB + s * CB + k] = rec;
+                    bm[s * CB + start] = k;
+                }
+                const uint32_t n_used = pc_total<CB>(used ? 1u : 0u);
+                const uint32_t adv = pc_total<CB>(used ? size : 0u);
+                const uint32_t cov = sg.rle_rem + pc_total<CB>(used ? nb : 0u);
+                const uint32_t nbad = pc_total<CB>(badk ? 1u : 0u);
+                const uint32_t r1 = sg.r + n_used, cur1 = sg.cursor + adv;
+                wave_sync();
+                if (here && k == 0) {
+                    PcSeg &ns = SEG[s];
+                    if (nbad > 0 || (bic > 0 && cov < bic)) ns.bad = 1;
+                    ns.r = r1;
+                    ns.cursor = cur1;
+                    ns.rle_rem = cov > bic ? cov - bic : 0u;
+                    ns.hbase = (4 + ((r1 * D * HB) >> 3)) & ~15u;
+                    ns.pbase = cur1 & ~15u;
+                }
+            }
+            wave_sync();
+            // ---- the next chunk's windows: loads in flight over the step ------
+            if (c + 1 < nchunks) stage_issue();
+        } else if (unpacker && t >= 1 && t <= nchunks) {
+            const uint32_t c = t - 1;
+            // ---- unpack ------------------------------------------------------
+            // One aligned two-dword LDS read and a funnel shift give 32
+            // payload bits: GF = 32 / W fields at once. Row-major payloads
+            // (fields of one row side by side): lanes = (segment, block, GF
+            // adjacent columns), one read per row. Column-major payloads (a
+            // column's 8 fields side by side): lanes = (segment, block,
+            // column), one read per GF rows. All LDS reads of the chunk's
+            // items are issued in three batches (block map, records, fields)
+            // so that their latency is paid three times per chunk rather than
+            // three times per item.
+            uint8_t *const zbuf = zb + (c & 1) * G::CHAINS * ZSTR;
+            const uint32_t *const bm = BM + (c & 1) * SPW * CB;
+            const u32x4 *const recs = REC + (c & 1) * SPW * CB;
+            constexpr uint32_t IP = G::IPASS, IL = G::IL, GF = G::GF;
+            constexpr uint32_t NRD = ROW ? 8 : 8 / GF;   // reads per item
+            uint32_t kk[IP];
+#pragma unroll
+            for (uint32_t ip = 0; ip < IP; ++ip) {
+                const uint32_t it = lane + 64 * ip;
+                const uint32_t b = (it / IL) % CB, s = ps0 + min(it / (IL * CB), SPP - 1);
+                kk[ip] = bm[s * CB + b];
+            }
+            u32x4 rr[IP];
+#pragma unroll
+            for (uint32_t ip = 0; ip < IP; ++ip) {
+                const uint32_t it = lane + 64 * ip;
+                const uint32_t s = ps0 + min(it / (IL * CB), SPP - 1);
+                rr[ip] = recs[s * CB + (kk[ip] & (CB - 1))];
+            }
+            // widths of the item's columns (0 past D), the bit offset of each
+            // field group and the 32 bits read there
+            uint32_t wdt[IP][ROW ? GF : 1], fw[IP][NRD];
+#pragma unroll
+            for (uint32_t ip = 0; ip < IP; ++ip) {
+                const uint32_t it = lane + 64 * ip;
+                const uint32_t q = it % IL;                       // column group (ROW) or column
+                const bool nz = it < G::ITEMS && kk[ip] != kPcZero;
+                const u32x4 rec = rr[ip];
+                constexpr uint32_t NCOL = ROW ? GF : 1;          // columns of the item
+                constexpr uint32_t CBITS = NCOL * HB;            // their header code bits
+                const uint32_t bp = q * CBITS;
+                const uint32_t cw = bp >= 32 ? rec.y >> (bp - 32) : __builtin_amdgcn_alignbit(rec.y, rec.x, bp);
+                uint32_t sum = 0;
+#pragma unroll
+                for (uint32_t g = 0; g < NCOL; ++g) {
+                    const uint32_t code = __builtin_amdgcn_ubfe(cw, g * HB, HB);
+                    const uint32_t width = nz && q * NCOL + g < (uint32_t)D ? code + ((code + 1) >> HB) : 0u;   // code w-1 stands for width w
+                    wdt[ip][ROW ? g : 0] = width;
+                    sum += width;
+                }
+                const uint32_t off = pc_incl<IL>(sum, q) - sum;  // bits before the item's first column
+                // ROW: field (i, first column) at rec.z + off + i * (row bits);
+                // column-major: fields GF*k .. GF*k+GF-1 at rec.z + 8*off + GF*k*width
+                const uint32_t p0 = nz ? rec.z + (ROW ? off : 8 * off) : 0u;
+                const uint32_t step = !nz ? 0u : ROW ? rec.w : GF * sum;
+#pragma unroll
+                for (uint32_t r = 0; r < NRD; ++r) {
+                    const uint32_t p = p0 + r * step;
+                    const uint32_t *qd = stgw + (p >> 5);
+                    fw[ip][r] = __builtin_amdgcn_alignbit(qd[1], qd[0], p);
+                }
+            }
+#pragma unroll
+            for (uint32_t ip = 0; ip < IP; ++ip) {
+                const uint32_t it = lane + 64 * ip;
+                const uint32_t q = it % IL, b = (it / IL) % CB, s = ps0 + min(it / (IL * CB), SPP - 1);
+                constexpr uint32_t NCOL = ROW ? GF : 1;
+                uint32_t o = 0;
+#pragma unroll
+                for (uint32_t g = 0; g < NCOL; ++g) {
+                    const uint32_t j = q * NCOL + g;
+                    const uint32_t w = wdt[ip][ROW ? g : 0];
+                    // the column's 8 zigzag codes
+                    uint32_t z[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        z[i] = ROW ? __builtin_amdgcn_ubfe(fw[ip][i], o, w)
+                                   : __builtin_amdgcn_ubfe(fw[ip][i / GF], (i % GF) * w, w);
+                    o += w;
+                    if (it < G::ITEMS && j < (uint32_t)D) {
+                        uint8_t *zp = zbuf + (s * D + j) * ZSTR + b * 8 * WB;
+                        // zigzag codes packed 2 (or 4) per dword, then unzigzagged
+                        // lane-wise: e = (z >> 1) ^ -(z & 1) in every 16-bit (8-bit) lane
+                        if (WB == 2) {
+                            u32x4 v;
+                            v.x = unzigzag16x2(z[0] | (z[1] << 16));
+                            v.y = unzigzag16x2(z[2] | (z[3] << 16));
+                            v.z = unzigzag16x2(z[4] | (z[5] << 16));
+                            v.w = unzigzag16x2(z[6] | (z[7] << 16));
+                            *reinterpret_cast<u32x4 *>(zp) = v;
+                        } else {
+                            uint2 v;
+                            v.x = unzigzag8x4(z[0] | (z[1] << 8) | (z[2] << 16) | (z[3] << 24));
+                            v.y = unzigzag8x4(z[4] | (z[5] << 8) | (z[6] << 16) | (z[7] << 24));
+                            *reinterpret_cast<uint2 *>(zp) = v;
+                        }
+                    }
+                }
+            }
+        } else if (consumer && t >= 2) {
+            const uint32_t c = t - 2;
+            // ---- recurrence: lane = column chain ------------------------------
+            const uint8_t *const zc = zb + (c & 1) * G::CHAINS * ZSTR + chain * ZSTR;
+            const uint32_t obase = cs * OSEG + cj * WB;
+            const uint32_t sh = c_sh;
+            const int32_t acc_lo = c_lo, acc_hi = c_hi;
+            // the whole chunk's errors first: one LDS wait per chunk
+            uint32_t evs[CB][4];
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                if (WB == 2) {
+                    const u32x4 v = *reinterpret_cast<const u32x4 *>(zc + 16 * b);
+                    evs[b][0] = v.x; evs[b][1] = v.y; evs[b][2] = v.z; evs[b][3] = v.w;
+                } else {
+                    const uint2 v = *reinterpret_cast<const uint2 *>(zc + 8 * b);
+                    evs[b][0] = v.x; evs[b][1] = v.y; evs[b][2] = 0; evs[b][3] = 0;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                const uint32_t *const ev = evs[b];
+                const int32_t alpha = acc >> sh;
+                int32_t grad = 0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    // e: the packed field read as a signed w-bit word (the
+                    // compiler takes it as a sign-extended SDWA operand)
+                    const uint32_t word = ev[WB == 2 ? i >> 1 : i >> 2];
+                    const int32_t e = WB == 2 ? ((i & 1) ? (int32_t)(int16_t)(word >> 16) : (int32_t)(int16_t)word)
+                                              : (int32_t)(int8_t)(word >> (8 * (i & 3)));
+                    if (FIRE) {
+                        // delta = e + floor(alpha * delta_prev / 2^w) modulo 2^w.
+                        // delta is kept unreduced: only its low w bits are
+                        // read, sign-extended, and |alpha * delta_prev| < 2^31
+                        // (2^15 for w = 8), so bits [w, 32) of the product
+                        // are the floor (wrapping add of e * 2^w gives the same
+                        // bits [w, 2w)).
+                        const int32_t p = pc_mul_sext<W>(alpha, delta);
+                        if (i & 1) grad += pc_mul_sext<W>(sgn_med3(e), delta);
+                        delta = (W == 16 ? (p >> 16) : (int32_t)(int8_t)(p >> 8)) + e;
+                        x += (uint32_t)delta;
+                    } else {
+                        x += (uint32_t)e;
+                    }
+                    const uint32_t o = obase + (uint32_t)((8 * b + i) * D * WB);
+                    if (WB == 1) outb[o] = (uint8_t)x;
+                    else *reinterpret_cast<uint16_t *>(outb + o) = (uint16_t)x;
+                }
+                if (FIRE) acc = min(max(acc + grad, acc_lo), acc_hi);
+            }
+            wave_sync();
+            // ---- output: each segment's rows of this chunk ---------------------
+            const uint32_t bic = c * CB < c_nb ? min((uint32_t)CB, c_nb - c * CB) : 0u;
+            const uint32_t valid = bic * 8 * D * WB;
+            // (lanes without a column chain have no rows: valid is 0 there)
+            uint8_t *const gp = c_on ? c_dst + (size_t)c * CB * 8 * D * WB : c_dst;
+#pragma unroll
+            for (uint32_t u = 0; u < G::UPL; ++u) {
+                const uint32_t lo = 16 * (cj + u * D);
+                if (lo + 16 <= valid) {
+                    u32x4 v;
+                    if (G::WIDE) {
+                        v = *reinterpret_cast<const u32x4 *>(outb + cs * OSEG + lo);
+                    } else {
+                        const uint32_t *p = reinterpret_cast<const uint32_t *>(outb + cs * OSEG + lo);
+                        v.x = p[0]; v.y = p[1]; v.z = p[2]; v.w = p[3];
+                    }
+                    gst128(gp + lo, v);
+                } else if (lo + 8 == valid) {
+                    const uint32_t *p = reinterpret_cast<const uint32_t *>(outb + cs * OSEG + lo);
+                    gst32(gp + lo, p[0]);
+                    gst32(gp + lo + 4, p[1]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- parser: final checks and raw tail rows (a stream's last segment) ------
+    if (parser) {
+        for (uint32_t s = 0; s < SPW; ++s) {
+            PcSeg &sg = SEG[s];
+            const uint32_t tb = sg.tail * D * WB;
+            if (sg.ok && (sg.r != sg.nrec || sg.rle_rem != 0 || sg.cursor + tb > sg.ext)) {
+                if (lane == 0) sg.bad = 1;
+            } else if (sg.ok) {
+                uint8_t *const tp = sg.dst + (size_t)sg.nrow * D * WB;
+                for (uint32_t q = lane; q < tb; q += 64) gst8(tp + q, gld8(sg.src + sg.cursor + q));
+            }
+        }
+        wave_sync();
+        if (lane < SPW && SEG[lane].bad && status) atomicOr(status + SEG[lane].status, 1);
+    }
+}
+
 // One container: workgroup b decodes segments [b * SPW, b * SPW + SPW).
 template <int W, bool FIRE, int D, int NP, int NC>
-__global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__restrict__ src, Geom g,
+__global__ __launch_bounds__(pc_single_threads(D, NP, NC)) void k_decode_pc(const uint8_t *__restrict__ src, Geom g,
                                                             typename Elem<W>::T *__restrict__ dst,
                                                             int32_t *__restrict__ status) {
     using G = PcGeom<W, D, kPcChunkBlocks, NP, NC>;
@@ -591,14 +981,15 @@ __global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc(const uint8_t *__r
         sg.sh = g.sh; sg.acc_lo = g.acc_lo; sg.acc_hi = g.acc_hi; sg.status = 0;
     };
     const uint32_t nchunks = ((g.S >> 3) + kPcChunkBlocks - 1) / kPcChunkBlocks;
-    pc_decode_group<W, FIRE, D, NP, NC>(nchunks, init, status);
+    if constexpr (pc_pipe(D)) pc_decode_group_pipe<W, FIRE, D, NP, NC>(nchunks, init, status);
+    else pc_decode_group<W, FIRE, D, NP, NC>(nchunks, init, status);
 }
 
 // Many containers: a persistent grid pulls groups of SPW work-list entries
 // (stream << 32 | segment, ~0 = empty) from a device queue; the segments of a
 // group share one seg_rows (group_s). Status bits go to status[stream].
 template <int W, bool FIRE, int D, int NP, int NC>
-__global__ __launch_bounds__(64 * (NP + NC)) void k_decode_pc_batch(const PcStream *__restrict__ streams,
+__global__ __launch_bounds__(pc_threads(NP, NC)) void k_decode_pc_batch(const PcStream *__restrict__ streams,
                                                                   const uint64_t *__restrict__ entries,
                                                                   const uint32_t *__restrict__ group_s, uint32_t ngroups,
                                                                   uint32_t *__restrict__ queue,

@@ -31,7 +31,7 @@ static void run_pc(const uint8_t *src, const spz::Geom &g, uint8_t *dst, int32_t
     for (uint32_t b = 0; b < grid; ++b) {
         emu::dim3e bid, bdim;
         bid.x = b;
-        bdim.x = 64 * (NP + NC);
+        bdim.x = spz::pc_single_threads(D, NP, NC);
         emu::run_block(bid, bdim, [&] {
             spz::k_decode_pc<W, FIRE, D, NP, NC>(src, g, reinterpret_cast<typename spz::Elem<W>::T *>(dst), status);
         });
