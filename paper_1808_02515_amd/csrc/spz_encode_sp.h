@@ -399,20 +399,49 @@ template <int W, bool FIRE, int D> __device__ __forceinline__ void es_encode_gro
 #pragma unroll
                 for (uint32_t pass = 0; pass < P; ++pass) {
                     const uint32_t s = (pass * IW + wave) * SPT + sl;
+                    // row-major: the fields of columns j and j + 1 of a row lie side
+                    // by side; even lanes take their odd neighbour's field and width
+                    // (every lane, before any lane-dependent branch) and write both
+                    // with one pair of atomics
+                    uint32_t zn[COL ? 1 : 8], wn = 0;
+                    if constexpr (!COL) {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) zn[i] = pc_dpp<0xF5>(z[pass][i]);   // quad_perm [1,1,3,3]
+                        wn = pc_dpp<0xF5>(width[pass]);
+                    }
                     if (valid[pass] && wsum[pass] != 0) {
                         const u32x4 res = BLK[wave][pass * NBS + bslot];
                         uint32_t *const pw = PST + s * PR * 4;
                         const uint32_t pbit = 8 * res.y;
                         const uint32_t wd = width[pass];
                         const uint32_t rbits = 8 * ((wsum[pass] + 7) >> 3);
-                        if (j < (uint32_t)D && wd != 0) {
+                        if (COL && j < (uint32_t)D && wd != 0) {
+                            // column-major: the column's fields lie side by side, so 32/w
+                            // of them (at most 32 bits) go in with one pair of atomics
+                            constexpr uint32_t FG = 32 / W;
 #pragma unroll
-                            for (int i = 0; i < 8; ++i) {
-                                const uint32_t p = COL ? pbit + 8 * off[pass] + (uint32_t)i * wd
-                                                       : pbit + (uint32_t)i * rbits + off[pass];
+                            for (uint32_t k = 0; k < 8 / FG; ++k) {
+                                uint32_t v = z[pass][k * FG];
+#pragma unroll
+                                for (uint32_t g = 1; g < FG; ++g) v |= z[pass][k * FG + g] << (g * wd);
+                                const uint32_t fwd = FG * wd;
+                                const uint32_t p = pbit + 8 * off[pass] + k * fwd;
                                 const uint32_t sb = p & 31u;
-                                atomicOr(&pw[(p >> 5) & (PR * 4 - 1)], z[pass][i] << sb);
-                                if (sb + wd > 32) atomicOr(&pw[((p >> 5) + 1) & (PR * 4 - 1)], z[pass][i] >> (32 - sb));
+                                atomicOr(&pw[(p >> 5) & (PR * 4 - 1)], v << sb);
+                                if (sb + fwd > 32) atomicOr(&pw[((p >> 5) + 1) & (PR * 4 - 1)], v >> (32 - sb));
+                            }
+                        }
+                        if constexpr (!COL) {
+                            if (!(j & 1) && j < (uint32_t)D && wd + wn != 0) {
+                                const uint32_t fwd = wd + wn;   // at most 2w <= 32 bits
+#pragma unroll
+                                for (int i = 0; i < 8; ++i) {
+                                    const uint32_t v = z[pass][i] | zn[i] << wd;
+                                    const uint32_t p = pbit + (uint32_t)i * rbits + off[pass];
+                                    const uint32_t sb = p & 31u;
+                                    atomicOr(&pw[(p >> 5) & (PR * 4 - 1)], v << sb);
+                                    if (sb + fwd > 32) atomicOr(&pw[((p >> 5) + 1) & (PR * 4 - 1)], v >> (32 - sb));
+                                }
                             }
                         }
                         if (j == 0) {
