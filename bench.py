@@ -148,6 +148,8 @@ def main():
     ap.add_argument("--batch-streams", type=int, default=10000,
                     help="stream workload: also run this many streams of the batch workload, batched vs one "
                          "launch per stream (0: skip)")
+    ap.add_argument("--huffman-streams", type=int, default=1024,
+                    help="huffman workload: streams of the batched-vs-per-stream leg")
     ap.add_argument("--batched-only", action="store_true",
                     help="batch workload: time only the batched calls (skip the one-launch-per-stream legs, "
                          "tens of thousands of dispatches, which counter collection serialises)")
@@ -710,8 +712,67 @@ def run_huffman(args, rows=1 << 29, D=4, S=2048):
         conts[name] = cont.cpu().numpy().tobytes() if not args.no_cpu_baseline else None
         del enc, ws, y
         torch.cuda.empty_cache()
+    # batched vs one call per stream: the same rows as K streams of rows / K
+    # rows, each coded with the Huffman stage; decoded (a) by one batched call
+    # (every segment of every stream Huffman-decoded in one launch, then the
+    # per-class batched decoder) and (b) by one sprintz_decompress_ws call per
+    # stream
+    K = args.huffman_streams
+    per = rows // K
+    parts = [x[k * per:(k + 1) * per] for k in range(K)]
+    bconts = [spz.compress(pt, "fire", S, entropy=1) for pt in parts]
+    torch.cuda.synchronize()
+    bd = spz.BatchDecoder(bconts)
+    bd.run()
+    torch.cuda.synchronize()
+    ev = _events(max(args.steps, 1))
+    for a, b in ev:
+        a.record()
+        bd.run()
+        b.record()
+    torch.cuda.synchronize()
+    bms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    bok = int(bd.status.abs().sum().item()) == 0 and all(
+        torch.equal(o.view(torch.uint8), pt.view(torch.uint8)) for o, pt in zip(bd.outs, parts))
+    binfos = [spz.info_of(c) for c in bconts]
+    bws = [torch.empty(max(spz.sprintz_decompress_workspace_size(i), 16), dtype=torch.uint8, device=dev) for i in binfos]
+    bst = torch.zeros(K, dtype=torch.int32, device=dev)
+
+    def per_stream():
+        for k in range(K):
+            rc = spz.sprintz_decompress_ws(bconts[k].data_ptr(), bconts[k].numel(), binfos[k], bd.outs[k].data_ptr(),
+                                           per * D * 2, bst[k:k + 1].data_ptr(), bws[k].data_ptr(), bws[k].numel(), sh)
+            if rc != spz.SPZ_OK:
+                raise spz.SprintzError(rc, "sprintz_decompress_ws")
+    per_stream()
+    torch.cuda.synchronize()
+    a, b = _events(1)[0]
+    a.record()
+    per_stream()
+    b.record()
+    torch.cuda.synchronize()
+    pms = a.elapsed_time(b)
+    bok = bok and int(bst.abs().sum().item()) == 0 and all(
+        torch.equal(o.view(torch.uint8), pt.view(torch.uint8)) for o, pt in zip(bd.outs, parts))
+    if not bok:
+        print("[bench] PARITY FAILURE huffman batch", file=sys.stderr, flush=True)
+        sys.exit(1)
+    UB = per * K * D * 2
+    CB_ = sum(c.numel() for c in bconts)
+    res["huffman_batch"] = {"streams": K, "rows_per_stream": per, "compressed_bytes": CB_,
+                            "batched_decode_GBps": round(UB / (bms * 1e-3) / 1e9, 2),
+                            "batched_decode_ms": round(bms, 3),
+                            "per_stream_decode_GBps": round(UB / (pms * 1e-3) / 1e9, 2),
+                            "per_stream_decode_ms": round(pms, 3),
+                            "batched_vs_per_stream": round(pms / bms, 2),
+                            "hbm_frac_batched": round((UB + CB_) / (bms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+    print(f"[bench] huffman batch: {res['huffman_batch']}", file=sys.stderr, flush=True)
+    bd.close()
+    del bd, bconts, bws, parts
+    torch.cuda.empty_cache()
     cpu = None
-    parity = "decoded samples equal to the input (both forms); encode repeatable"
+    parity = ("decoded samples equal to the input (both forms, and every stream of the batched and per-stream "
+              "decodes); encode repeatable")
     if not args.no_cpu_baseline:
         # oracle leg: segments 0, nseg/3, 2 nseg/3, last coded alone by the
         # oracle must equal the GPU container's segments; timed as the baseline
@@ -741,9 +802,11 @@ def run_huffman(args, rows=1 << 29, D=4, S=2048):
         "value": res["huffman"]["decode_GBps"], "unit": "GB/s", "n_gpus": 1, "steps": max(args.steps, 1),
         "warmup": 1, "ms_per_step": res["huffman"]["decode_ms"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u16", "data": "synthetic",
-        "config": {"workload": f"laplace_walk_uint16 {rows}x{D} scale 3 fire seg_rows={S}, Huffman vs plain"},
+        "config": {"workload": f"laplace_walk_uint16 {rows}x{D} scale 3 fire seg_rows={S}, Huffman vs plain; "
+                               f"the same rows as {args.huffman_streams} Huffman-coded streams, batched vs per stream"},
         "value_note": "decode GB/s of the Huffman-coded form",
-        "plain": res["plain"], "huffman": res["huffman"], "parity": parity, "roofline": None, "cpu_baseline": cpu,
+        "plain": res["plain"], "huffman": res["huffman"], "huffman_batch": res["huffman_batch"], "parity": parity,
+        "roofline": None, "cpu_baseline": cpu,
         "paper_context": "paper Section 5.4: with Huffman coding decompression stays above 500 MB/s (one CPU thread)",
     }
     print(json.dumps(out), flush=True)

@@ -192,8 +192,8 @@ size_t sprintz_decompress_workspace_size(const spz_info *info);
  * Entropy Coding), then decoded as by sprintz_decompress. A corrupt coded segment
  * sets bit 2 of *d_status. sprintz_decompress on an entropy-coded container
  * does the same with a stream-ordered allocation (hipMallocAsync /
- * hipFreeAsync) of the workspace. Batched plans reject entropy-coded
- * containers (SPZ_EUNSUPPORTED). */
+ * hipFreeAsync) of the workspace. Batched plans take entropy-coded
+ * containers too (their plain containers live in the plan's workspace). */
 spz_status sprintz_decompress_ws(const void *d_src, size_t src_size, const spz_info *info, void *d_dst,
                                  size_t dst_cap, int32_t *d_status, void *d_ws, size_t ws_size, hipStream_t stream);
 
@@ -209,7 +209,10 @@ spz_status sprintz_decompress_ws(const void *d_src, size_t src_size, const spz_i
  * Streams outside the batched kernels (hdr_group != 0, D > 16, output not
  * 16-byte aligned, seg_rows * D * w/8 not a multiple of 16) are decoded by
  * the single-container path inside the same call. Entropy-coded containers
- * are rejected (SPZ_EUNSUPPORTED). */
+ * (params.entropy = 1, Section 4.4) are first Huffman-decoded, all their
+ * segments in one launch, into plain containers in the plan's workspace
+ * (sprintz_decompress_workspace_size bytes each, rounded up to 256), which
+ * then take the same batched or single-container path. */
 typedef struct {
     const void *d_src;   /* container, 16-byte aligned, src_size bytes */
     size_t src_size;
@@ -228,7 +231,8 @@ typedef struct spz_batch spz_batch;
  * keeps the buffers alive and unchanged in size while the plan is used. */
 spz_status sprintz_batch_create(const spz_batch_item *items, const spz_info *infos, uint32_t n, spz_batch **out);
 
-/* Device bytes of the plan tables for these items (0 if an item is invalid). */
+/* Device bytes of the plan for these items: the plain containers of
+ * entropy-coded items, then the tables (0 if an item is invalid). */
 size_t sprintz_batch_workspace_size(const spz_batch_item *items, const spz_info *infos, uint32_t n);
 
 /* As sprintz_batch_create, but the tables go to the caller's device workspace

@@ -364,8 +364,9 @@ static spz_status compress_entropy(const void *d_src, uint64_t rows, uint32_t D,
     spz_params pp = *p;
     pp.entropy = 0;
     const uint64_t nseg = num_segments(rows, p->seg_rows);
-    const uint64_t ldsb = spz::huff_segment_bound(plain_segment_max(rows, D, w, p));
-    if (nseg > 0 && ldsb > kHufLdsMax) return SPZ_EUNSUPPORTED;
+    // LDS image of the write pass: the largest coded segment, at most
+    // kHufLdsMax (larger segments are written in place in the container)
+    const uint64_t ldsb = std::min<uint64_t>(spz::huff_segment_bound(plain_segment_max(rows, D, w, p)), kHufLdsMax);
     const size_t plain_cap = sprintz_compress_bound(rows, D, dtype, &pp);
     const size_t plain_ws = sprintz_workspace_size(rows, D, dtype, &pp);
     uint8_t *P = (uint8_t *)d_ws;
@@ -794,6 +795,12 @@ struct spz_batch {
     uint32_t *queues;                              // one work counter per class
     double work[kClasses];                         // launch order weight per class
     Lanes lanes;
+    // entropy-coded items: one Huffman decode job each, decoded by one batched
+    // launch into plain containers in the plan's workspace (past the tables)
+    spz::HufJob *hjobs;
+    uint64_t *hentries;                            // job << 32 | segment
+    uint32_t nhent;
+    size_t img_off, total;                         // workspace: plain containers, then the tables at img_off
     // streams that take the single-container path
     struct Fallback { const void *src; void *dst; spz_info info; spz::Geom g; uint32_t index; };
     Fallback *fallback;
@@ -860,12 +867,25 @@ spz_status build_plan(const spz_batch_item *items, const spz_info *infos, uint32
     b->n = n;
     std::vector<spz::Geom> geoms(n);
     std::vector<int> cls(n, -1);
+    // entropy-coded items decode from a plain container in the workspace:
+    // their plain geometry and stride, and the coded container's geometry
+    std::vector<spz::Geom> cgeoms(n);
+    std::vector<uint64_t> pstride(n, 0);
+    std::vector<spz_info> pinfo(infos, infos + n);
     for (uint32_t i = 0; i < n; ++i) {
         const spz_status st =
             check_decompress(items[i].d_src, items[i].src_size, &infos[i], items[i].d_dst, items[i].dst_cap, &geoms[i]);
         if (st != SPZ_OK) return st;
         const spz_info &in = infos[i];
-        if (in.params.entropy != 0) return SPZ_EUNSUPPORTED;
+        if (in.params.entropy > 1) return SPZ_EUNSUPPORTED;
+        if (in.params.entropy == 1 && in.nseg > 0) {
+            cgeoms[i] = geoms[i];
+            pstride[i] = plain_segment_max(in.rows, in.D, in.w, &in.params);
+            pinfo[i].params.entropy = 0;
+            pinfo[i].compressed_size = geoms[i].data_start + pstride[i] * in.nseg;
+            geoms[i].data_bytes = pstride[i] * in.nseg;
+            geoms[i].cap = pinfo[i].compressed_size;
+        }
         const uint32_t D = in.D;
         if (D >= 1 && D <= 16 && in.params.hdr_group == 0 && !((uintptr_t)items[i].d_dst & 15) &&
             ((uint64_t)in.params.seg_rows * D * (in.w / 8)) % 16 == 0 && in.nseg > 0)
@@ -880,11 +900,26 @@ spz_status build_plan(const spz_batch_item *items, const spz_info *infos, uint32
     std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
         return infos[x].params.seg_rows < infos[y].params.seg_rows;
     });
+    // the plain containers of entropy-coded items come first in the
+    // workspace, the tables after them
+    std::vector<size_t> poff(n, 0);
+    size_t P = 0;
+    uint32_t njobs = 0;
+    uint64_t nhent = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!pstride[i]) continue;
+        poff[i] = P;
+        P += align256(pinfo[i].compressed_size);
+        ++njobs;
+        nhent += infos[i].nseg;
+    }
+    if (nhent > 0xFFFFFFFFull) return SPZ_EUNSUPPORTED;
+    auto srcof = [&](uint32_t i) -> const void * { return pstride[i] ? (const void *)(base + poff[i]) : items[i].d_src; };
     std::vector<spz_batch::Fallback> fb;
     for (uint32_t oi = 0; oi < n; ++oi) {
         const uint32_t i = order[oi];
         if (cls[i] < 0) {
-            if (infos[i].rows > 0) fb.push_back({items[i].d_src, items[i].d_dst, infos[i], geoms[i], i});
+            if (infos[i].rows > 0) fb.push_back({srcof(i), items[i].d_dst, pinfo[i], geoms[i], i});
             continue;
         }
         const int c = cls[i];
@@ -898,7 +933,8 @@ spz_status build_plan(const spz_batch_item *items, const spz_info *infos, uint32
             ent[c].push_back(((uint64_t)i << 32) | sg);
         }
     }
-    size_t bytes = sizeof(spz::PcStream) * (size_t)n + 16 + sizeof(uint32_t) * kClasses;
+    size_t bytes = sizeof(spz::PcStream) * (size_t)n + 16 + sizeof(uint32_t) * kClasses + 16 +
+                   sizeof(spz::HufJob) * njobs + 16 + 8 * (size_t)nhent + 16;
     for (int c = 0; c < kClasses; ++c) {
         const uint32_t spw = spz::pc_spw(class_D(c), spz::kPcProducers, spz::kPcConsumers);
         while (ent[c].size() % spw) ent[c].push_back(~0ull);
@@ -914,7 +950,7 @@ spz_status build_plan(const spz_batch_item *items, const spz_info *infos, uint32
         const spz_info &in = infos[i];
         const spz::Geom &g = geoms[i];
         spz::PcStream &st = hs[i];
-        st.src = (const uint8_t *)items[i].d_src;
+        st.src = (const uint8_t *)srcof(i);
         st.dst = (uint8_t *)items[i].d_dst;
         st.data_start = g.data_start;
         st.data_bytes = g.data_bytes;
@@ -934,11 +970,41 @@ spz_status build_plan(const spz_batch_item *items, const spz_info *infos, uint32
         if (!gs[c].empty()) memcpy(host.data() + o_gs[c], gs[c].data(), gs[c].size() * 4);
     }
     const size_t o_q = carve(sizeof(uint32_t) * kClasses);
-    b->streams = (spz::PcStream *)(base + o_streams);
-    b->queues = (uint32_t *)(base + o_q);
+    const size_t o_jobs = carve(sizeof(spz::HufJob) * njobs);
+    const size_t o_hent = carve(8 * (size_t)nhent);
+    {
+        spz::HufJob *hj = reinterpret_cast<spz::HufJob *>(host.data() + o_jobs);
+        uint64_t *he = reinterpret_cast<uint64_t *>(host.data() + o_hent);
+        uint32_t j = 0;
+        uint64_t q = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            if (!pstride[i]) continue;
+            spz::HufJob &job = hj[j];
+            job.src = (const uint8_t *)items[i].d_src;
+            job.plain = base + poff[i];
+            job.src_size = items[i].src_size;
+            job.data_start = cgeoms[i].data_start;
+            job.data_bytes = cgeoms[i].data_bytes;
+            job.stride = pstride[i];
+            job.nseg = infos[i].nseg;
+            job.table = 1;
+            job.status = i;
+            job.pad = 0;
+            for (uint32_t sg = 0; sg < infos[i].nseg; ++sg) he[q++] = ((uint64_t)j << 32) | sg;
+            ++j;
+        }
+    }
+    uint8_t *const tb = base + P;   // the tables, after the plain containers
+    b->img_off = P;
+    b->total = P + host.size();
+    b->hjobs = (spz::HufJob *)(tb + o_jobs);
+    b->hentries = (uint64_t *)(tb + o_hent);
+    b->nhent = (uint32_t)nhent;
+    b->streams = (spz::PcStream *)(tb + o_streams);
+    b->queues = (uint32_t *)(tb + o_q);
     for (int c = 0; c < kClasses; ++c) {
-        b->entries[c] = (uint64_t *)(base + o_ent[c]);
-        b->group_s[c] = (uint32_t *)(base + o_gs[c]);
+        b->entries[c] = (uint64_t *)(tb + o_ent[c]);
+        b->group_s[c] = (uint32_t *)(tb + o_gs[c]);
         b->ngroups[c] = (uint32_t)gs[c].size();
         uint32_t cap = 1;
 #define SPZ_CAP(W_, F_, D_) if (class_w(c) == W_ && class_fire(c) == F_ && class_D(c) == D_) cap = batch_grid_cap<W_, F_, D_>();
@@ -973,7 +1039,7 @@ size_t sprintz_batch_workspace_size(const spz_batch_item *items, const spz_info 
     spz_batch b{};
     if (build_plan(items, infos, n, &b, nullptr) != SPZ_OK) { delete[] b.fallback; return 0; }
     delete[] b.fallback;
-    return b.host.size();
+    return b.total;
 }
 
 spz_status sprintz_batch_create(const spz_batch_item *items, const spz_info *infos, uint32_t n, spz_batch **out) {
@@ -985,10 +1051,11 @@ spz_status sprintz_batch_create(const spz_batch_item *items, const spz_info *inf
     if (st != SPZ_OK) { delete[] b->fallback; delete b; return st; }
     delete[] b->fallback;
     b->fallback = nullptr;
-    if (hipMalloc(&b->dmem, b->host.size()) != hipSuccess) { delete b; return SPZ_ENOMEM; }
+    if (hipMalloc(&b->dmem, b->total) != hipSuccess) { delete b; return SPZ_ENOMEM; }
     b->owns = true;
     st = build_plan(items, infos, n, b, (uint8_t *)b->dmem);
-    if (st == SPZ_OK && hipMemcpy(b->dmem, b->host.data(), b->host.size(), hipMemcpyHostToDevice) != hipSuccess)
+    if (st == SPZ_OK && hipMemcpy((uint8_t *)b->dmem + b->img_off, b->host.data(), b->host.size(),
+                                  hipMemcpyHostToDevice) != hipSuccess)
         st = SPZ_EHIP;
     if (st == SPZ_OK && b->lanes.create() != hipSuccess) st = SPZ_EHIP;
     if (st != SPZ_OK) { b->lanes.destroy(); (void)hipFree(b->dmem); delete[] b->fallback; delete b; return st; }
@@ -1003,9 +1070,9 @@ spz_status sprintz_batch_create_in(const spz_batch_item *items, const spz_info *
     spz_batch *b = new (std::nothrow) spz_batch();
     if (!b) return SPZ_ENOMEM;
     spz_status st = build_plan(items, infos, n, b, (uint8_t *)d_ws);
-    if (st == SPZ_OK && b->host.size() > ws_size) st = SPZ_ENOSPC;
-    if (st == SPZ_OK &&
-        hipMemcpyAsync(d_ws, b->host.data(), b->host.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
+    if (st == SPZ_OK && b->total > ws_size) st = SPZ_ENOSPC;
+    if (st == SPZ_OK && hipMemcpyAsync((uint8_t *)d_ws + b->img_off, b->host.data(), b->host.size(),
+                                       hipMemcpyHostToDevice, stream) != hipSuccess)
         st = SPZ_EHIP;
     if (st == SPZ_OK && b->lanes.create() != hipSuccess) st = SPZ_EHIP;
     if (st != SPZ_OK) { b->lanes.destroy(); delete[] b->fallback; delete b; return st; }
@@ -1019,6 +1086,11 @@ spz_status sprintz_batch_create_in(const spz_batch_item *items, const spz_info *
 spz_status sprintz_batch_decompress(const spz_batch *b, int32_t *d_status, hipStream_t stream) {
     if (!b) return SPZ_EINVAL;
     hipLaunchKernelGGL(spz::k_zero_u32, dim3(1), dim3(64), 0, stream, b->queues, (uint32_t)kClasses);
+    // entropy-coded items: every segment Huffman-decoded into its plain
+    // container (and the containers' tables written) in one launch
+    if (b->nhent)
+        hipLaunchKernelGGL(spz::k_huff_decode_batch, dim3((b->nhent + spz::kHufSegsPerWave - 1) / spz::kHufSegsPerWave),
+                           dim3(64), 0, stream, b->hjobs, b->hentries, b->nhent, d_status);
     int order[kClasses];
     const int ncls = lane_order(b->ngroups, [&](int c) { return b->work[c]; }, order);
     const int used = std::min(ncls, kLanes);

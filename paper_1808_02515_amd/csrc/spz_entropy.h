@@ -23,7 +23,9 @@
 //   k_huff_scan   offsets of the coded segments, container header
 //   k_huff_write  one workgroup per segment: canonical codes, every byte's
 //                 code OR-ed into an LDS image of the coded segment at its
-//                 bit offset (scans over the byte ranges), 16-byte stores.
+//                 bit offset (scans over the byte ranges), 16-byte stores;
+//                 a coded segment larger than the LDS image is OR-ed into
+//                 its (cleared) place in the container directly.
 // Decompression runs
 //   k_huff_decode one wavefront per four segments, 16 lanes per segment: a
 //                 2048-entry table (11-bit lookup) per segment in LDS, one
@@ -235,7 +237,6 @@ __global__ __launch_bounds__(256) void k_huff_write(const uint8_t *__restrict__ 
     extern __shared__ u32x4 img4[];
     __shared__ uint32_t len[256], rcode[256], cntl[kHufMaxLen + 1], first[kHufMaxLen + 1];
     __shared__ uint32_t sub_base[kHufSub];
-    uint32_t *img = reinterpret_cast<uint32_t *>(img4);
     const uint32_t t = threadIdx.x, s = blockIdx.x;
     if (s >= nseg) return;
     const uint64_t a = gld64(plain + 64 + 8ull * s), b = gld64(plain + 64 + 8ull * (s + 1));
@@ -243,87 +244,121 @@ __global__ __launch_bounds__(256) void k_huff_write(const uint8_t *__restrict__ 
     const uint32_t n = (uint32_t)(b - a), m16 = n / kHufSub;
     const uint8_t *rec = info + (uint64_t)s * kHufInfo;
     const uint32_t coded = reinterpret_cast<const uint32_t *>(rec + 192)[0];
-    if (coded > ldsb) {
-        if (t == 0 && status) atomicOr(status, 2);
-        return;
-    }
-    for (uint32_t k = t; k < coded / 4; k += 256) img[k] = 0;
-    const uint32_t lv = (gld8(rec + (t >> 1)) >> (4 * (t & 1))) & 15u;
-    len[t] = lv;
-    if (t <= kHufMaxLen) cntl[t] = 0;
-    __syncthreads();
-    if (lv) atomicAdd(&cntl[lv], 1u);
-    if (t < kHufSub) {
-        uint32_t base = kHufFixed;
-        for (uint32_t k = 0; k < t; ++k) base += reinterpret_cast<const uint32_t *>(rec + 128)[k];
-        sub_base[t] = base;
-    }
-    __syncthreads();
-    if (t == 0) {
-        uint32_t c = 0;
-        for (uint32_t l = 1; l <= kHufMaxLen; ++l) {
-            first[l] = c;
-            c = (c + cntl[l]) << 1;
-        }
-    }
-    __syncthreads();
-    {
-        uint32_t r = 0;
-        for (uint32_t u = 0; u < t; ++u) r += len[u] == lv ? 1u : 0u;
-        rcode[t] = lv ? huff_rev(first[lv] + r, lv) : 0u;
-    }
-    // fixed part: n, lengths, sub-stream sizes (bytes 0..195; streams start at 196)
-    if (t < 49) {
-        uint32_t word;
-        if (t == 0) word = n;
-        else if (t <= 32) word = gld32(rec + 4 * (t - 1));
-        else word = reinterpret_cast<const uint32_t *>(rec + 128)[t - 33];
-        img[t] = word;
-    }
-    __syncthreads();
-    // thread = (sub-stream k, part p): bit offsets by a scan over the parts
-    const uint32_t k = t >> 4, p = t & 15;
-    const uint32_t q = (m16 + 15) / 16;
-    const uint32_t lo = min(p * q, m16), hi = min(lo + q, m16);
-    const uint8_t *src = seg + k * m16;
-    uint32_t bits = 0;
-    for (uint32_t i = lo; i < hi; ++i) bits += len[gld8(src + i)];
-    uint32_t incl = bits;
-#pragma unroll
-    for (uint32_t d = 1; d < 16; d <<= 1) {
-        const uint32_t o = (uint32_t)__shfl_up((int)incl, d, 16);
-        if (p >= d) incl += o;
-    }
-    uint32_t pos = 8 * sub_base[k] + incl - bits;
-    for (uint32_t i = lo; i < hi; ++i) {
-        const uint32_t v = gld8(src + i);
-        const uint32_t l = len[v], rc = rcode[v];
-        atomicOr(&img[pos >> 5], rc << (pos & 31));
-        if ((pos & 31) + l > 32) atomicOr(&img[(pos >> 5) + 1], rc >> (32 - (pos & 31)));
-        pos += l;
-    }
-    __syncthreads();
     const uint64_t ta = gld64(dst + 64 + 8ull * s);
-    uint8_t *out = dst + data_start + ta;
-    for (uint32_t u = t; u < coded / 16; u += 256) gst128(out + 16 * u, img4[u]);
+    uint8_t *const out = dst + data_start + ta;
+    // the coded image: in LDS when it fits (ldsb bytes), else the destination
+    // itself, cleared first (the offsets are final: the scan ran before)
+    const bool in_lds = coded <= ldsb;
+    auto body = [&](uint32_t *img) {
+        for (uint32_t k = t; k < coded / 4; k += 256) img[k] = 0;
+        if (!in_lds) __threadfence();
+        const uint32_t lv = (gld8(rec + (t >> 1)) >> (4 * (t & 1))) & 15u;
+        len[t] = lv;
+        if (t <= kHufMaxLen) cntl[t] = 0;
+        __syncthreads();
+        if (lv) atomicAdd(&cntl[lv], 1u);
+        if (t < kHufSub) {
+            uint32_t base = kHufFixed;
+            for (uint32_t k = 0; k < t; ++k) base += reinterpret_cast<const uint32_t *>(rec + 128)[k];
+            sub_base[t] = base;
+        }
+        __syncthreads();
+        if (t == 0) {
+            uint32_t c = 0;
+            for (uint32_t l = 1; l <= kHufMaxLen; ++l) {
+                first[l] = c;
+                c = (c + cntl[l]) << 1;
+            }
+        }
+        __syncthreads();
+        {
+            uint32_t r = 0;
+            for (uint32_t u = 0; u < t; ++u) r += len[u] == lv ? 1u : 0u;
+            rcode[t] = lv ? huff_rev(first[lv] + r, lv) : 0u;
+        }
+        // fixed part: n, lengths, sub-stream sizes (bytes 0..195; streams start at 196)
+        if (t < 49) {
+            uint32_t word;
+            if (t == 0) word = n;
+            else if (t <= 32) word = gld32(rec + 4 * (t - 1));
+            else word = reinterpret_cast<const uint32_t *>(rec + 128)[t - 33];
+            img[t] = word;
+        }
+        __syncthreads();
+        // thread = (sub-stream k, part p): bit offsets by a scan over the parts
+        const uint32_t k = t >> 4, p = t & 15;
+        const uint32_t q = (m16 + 15) / 16;
+        const uint32_t lo = min(p * q, m16), hi = min(lo + q, m16);
+        const uint8_t *src = seg + k * m16;
+        uint32_t bits = 0;
+        for (uint32_t i = lo; i < hi; ++i) bits += len[gld8(src + i)];
+        uint32_t incl = bits;
+#pragma unroll
+        for (uint32_t d = 1; d < 16; d <<= 1) {
+            const uint32_t o = (uint32_t)__shfl_up((int)incl, d, 16);
+            if (p >= d) incl += o;
+        }
+        uint32_t pos = 8 * sub_base[k] + incl - bits;
+        for (uint32_t i = lo; i < hi; ++i) {
+            const uint32_t v = gld8(src + i);
+            const uint32_t l = len[v], rc = rcode[v];
+            atomicOr(&img[pos >> 5], rc << (pos & 31));
+            if ((pos & 31) + l > 32) atomicOr(&img[(pos >> 5) + 1], rc >> (32 - (pos & 31)));
+            pos += l;
+        }
+    };
+    if (in_lds) {
+        body(reinterpret_cast<uint32_t *>(img4));
+        __syncthreads();
+        for (uint32_t u = t; u < coded / 16; u += 256) gst128(out + 16 * u, img4[u]);
+    } else {
+        body(reinterpret_cast<uint32_t *>(out));
+    }
 }
 
 // ---- decode --------------------------------------------------------------
+// One entropy-coded container whose segments a decode wavefront takes.
+struct HufJob {
+    const uint8_t *src;         // coded container
+    uint8_t *plain;             // plain container at a fixed segment stride
+    uint64_t src_size, data_start, data_bytes, stride;
+    uint32_t nseg, table;       // segments; nonzero: also write the plain header and offset table
+    uint32_t status, pad;       // index of its status word
+};
+
 // Lanes (segment g of the wavefront's four, sub-stream k). Plain segment s
-// goes to plain + data_start + s * stride.
-__global__ __launch_bounds__(64) void k_huff_decode(const uint8_t *__restrict__ src, uint64_t src_size,
-                                                    uint64_t data_start, uint64_t data_bytes, uint32_t nseg,
-                                                    uint8_t *__restrict__ plain, uint64_t stride,
-                                                    int32_t *__restrict__ status) {
+// of job jb goes to jb.plain + data_start + s * stride; `have` is false for
+// lanes whose group has no segment (they take part in the wave's syncs).
+// With jb.table the group of segment s also writes its offset-table entries
+// (and segment 0's group the header: the coded one's, entropy 0, data bytes
+// nseg * stride).
+__device__ __forceinline__ void huff_decode_wave(const HufJob &jb, uint32_t s, bool have, int32_t *__restrict__ statuses) {
     __shared__ uint16_t lut[kHufSegsPerWave][1u << kHufMaxLen];
     __shared__ uint32_t cnt[kHufSegsPerWave][kHufSub][kHufMaxLen + 1];
     __shared__ uint32_t first[kHufSegsPerWave][kHufMaxLen + 1];
     __shared__ uint32_t index[kHufSegsPerWave][kHufMaxLen + 1];   // first position of each length in code order
     __shared__ uint32_t codes_end[kHufSegsPerWave];              // end of the used 11-bit code space
     __shared__ uint8_t sorted[kHufSegsPerWave][256];             // values in (length, value) order
-    const uint32_t lane = threadIdx.x, g = lane >> 4, k = lane & 15;
-    const uint32_t s = blockIdx.x * kHufSegsPerWave + g;
-    bool ok = s < nseg;
+    const uint32_t lane = threadIdx.x & 63, g = lane >> 4, k = lane & 15;
+    const uint8_t *const src = jb.src;
+    uint8_t *const plain = jb.plain;
+    const uint64_t src_size = jb.src_size, data_start = jb.data_start, data_bytes = jb.data_bytes;
+    const uint64_t stride = jb.stride;
+    const uint32_t nseg = jb.nseg;
+    int32_t *const status = statuses ? statuses + jb.status : nullptr;
+    if (have && jb.table && s < nseg) {
+        uint64_t *const tab = reinterpret_cast<uint64_t *>(plain + 64);
+        if (k == 0) tab[s] = (uint64_t)s * stride;
+        if (k == 1 && s + 1 == nseg) tab[nseg] = (uint64_t)nseg * stride;
+        if (s == 0) {
+            uint32_t word = gld32(src + 4 * k);
+            if (k == 2) word &= 0x00FFFFFFu;   // entropy 0
+            if (k == 8) word = (uint32_t)(stride * nseg);
+            if (k == 9) word = (uint32_t)((stride * nseg) >> 32);
+            reinterpret_cast<uint32_t *>(plain)[k] = word;
+        }
+    }
+    bool ok = have && s < nseg;
     uint64_t a = 0, b = 0;
     if (ok) {
         a = gld64(src + 64 + 8ull * s);
@@ -494,7 +529,30 @@ __global__ __launch_bounds__(64) void k_huff_decode(const uint8_t *__restrict__ 
         }
     }
     if (bad || used > 8u * size) ok = false;
-    if (s < nseg && !ok && status) atomicOr(status, 4);
+    if (have && s < nseg && !ok && status) atomicOr(status, 4);
+}
+
+__global__ __launch_bounds__(64) void k_huff_decode(const uint8_t *__restrict__ src, uint64_t src_size,
+                                                    uint64_t data_start, uint64_t data_bytes, uint32_t nseg,
+                                                    uint8_t *__restrict__ plain, uint64_t stride,
+                                                    int32_t *__restrict__ status) {
+    HufJob jb;
+    jb.src = src; jb.plain = plain;
+    jb.src_size = src_size; jb.data_start = data_start; jb.data_bytes = data_bytes; jb.stride = stride;
+    jb.nseg = nseg; jb.table = 0; jb.status = 0; jb.pad = 0;
+    huff_decode_wave(jb, blockIdx.x * kHufSegsPerWave + (threadIdx.x >> 4), true, status);
+}
+
+// Many containers: entry e = job << 32 | segment; a wavefront takes four
+// consecutive entries and also writes the plain containers' tables. Corrupt
+// coded segments of job j set bit 2 of status[jobs[j].status].
+__global__ __launch_bounds__(64) void k_huff_decode_batch(const HufJob *__restrict__ jobs,
+                                                          const uint64_t *__restrict__ entries, uint32_t nent,
+                                                          int32_t *__restrict__ status) {
+    const uint32_t q = blockIdx.x * kHufSegsPerWave + (threadIdx.x >> 4);
+    const bool have = q < nent;
+    const uint64_t e = have ? entries[q] : 0ull;
+    huff_decode_wave(jobs[have ? (uint32_t)(e >> 32) : 0u], (uint32_t)e, have, status);
 }
 
 // Header and offset table of the workspace (plain) container.

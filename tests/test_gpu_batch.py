@@ -179,3 +179,73 @@ def test_batch_large_plan_and_graph_replays():
         for x, o in zip(xs, bd.outs):
             assert torch.equal(o.view(torch.int16), x), rep
     bd.close()
+
+
+def _entropy_cases(seed=21):
+    """Entropy-coded oracle containers beside plain ones: batched classes
+    (D 1..16, both widths), a single-container one (D = 20) and grouped
+    headers; Laplace walks whose codes hit the length limit."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    for k in range(14):
+        D = int(rng.choice([1, 2, 4, 8, 16]))
+        rows = int(rng.integers(8, 4000))
+        if k % 3 == 0:
+            x = datagen.laplace_walk_uint16(rows, D, seed=300 + k)
+        else:
+            x = datagen.ar2_uint16(rows, D, sigma=float(rng.uniform(1, 100)), seed=300 + k).astype(
+                [np.int8, np.uint16][k % 2])
+        S = 1024 if (1024 * D * x.dtype.itemsize) % 16 == 0 else 2048
+        cases.append((x, "fire", S, 0, k % 2))
+    cases.append((datagen.walk_int8(1500, 20, seed=9), "fire", 1024, 0, 1))
+    cases.append((datagen.ar2_uint16(1200, 8, seed=10), "fire", 256, 2, 1))
+    return cases
+
+
+def test_batch_entropy_coded_containers():
+    cases = _entropy_cases()
+    blobs = [oracle.compress(x, f, S, G, entropy=e) for x, f, S, G, e in cases]
+    conts = [_dev(b) for b in blobs]
+    _say(f"batch of {len(conts)} streams, {sum(e for *_, e in cases)} entropy-coded")
+    bd = spz.BatchDecoder(conts)
+    for rep in range(2):
+        for o in bd.outs:
+            o.view(torch.uint8).fill_(0x33)
+        bd.status.zero_()
+        bd.run()
+        torch.cuda.synchronize()
+        assert int(bd.status.abs().sum().item()) == 0
+        for i, (x, f, S, G, e) in enumerate(cases):
+            assert np.array_equal(_np(bd.outs[i], x.dtype).reshape(x.shape), x), (rep, i, x.shape, x.dtype, S, G, e)
+    # a captured graph of the same call, replayed with eager work between
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        bd.run(stream=s)
+    for rep in range(3):
+        for o in bd.outs:
+            o.view(torch.uint8).fill_(rep + 1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(bd.status.abs().sum().item()) == 0
+        for i, (x, f, S, G, e) in enumerate(cases):
+            assert np.array_equal(_np(bd.outs[i], x.dtype).reshape(x.shape), x), ("replay", rep, i)
+    bd.close()
+
+
+def test_batch_corrupt_entropy_container_is_flagged():
+    xs = [datagen.laplace_walk_uint16(3000, 4, seed=70 + k) for k in range(3)]
+    blobs = [bytearray(oracle.compress(x, "fire", 1024, entropy=1)) for x in xs]
+    ds = (64 + 8 * (int.from_bytes(blobs[1][28:32], "little") + 1) + 15) & ~15
+    for p in range(ds + 200, len(blobs[1]), 61):
+        blobs[1][p] ^= 0xA5
+    conts = [_dev(bytes(b)) for b in blobs]
+    bd = spz.BatchDecoder(conts)
+    bd.run()
+    torch.cuda.synchronize()
+    st = bd.status.cpu().numpy()
+    assert st[1] != 0 and st[0] == 0 and st[2] == 0
+    for k in (0, 2):
+        assert np.array_equal(_np(bd.outs[k], np.uint16).reshape(xs[k].shape), xs[k])
+    bd.close()

@@ -129,22 +129,28 @@ def test_entropy_corrupt_segments_flag_status_and_stay_in_bounds():
         run(bad)
 
 
-def test_entropy_unsupported_cases():
-    # a segment whose coded image does not fit the write pass's LDS
-    p = spz.make_params("fire", 65536, entropy=1)
-    x = torch.zeros((65536, 16), dtype=torch.int16, device="cuda")
-    enc_cap = spz.sprintz_compress_bound(65536, 16, spz.SPZ_INT16, p)
-    wsz = spz.sprintz_workspace_size(65536, 16, spz.SPZ_INT16, p)
-    dst = torch.empty(enc_cap, dtype=torch.uint8, device="cuda")
-    ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
-    osz = torch.zeros(1, dtype=torch.int64, device="cuda")
-    rc = spz.sprintz_compress(x.data_ptr(), 65536, 16, spz.SPZ_INT16, p, dst.data_ptr(), enc_cap, osz.data_ptr(),
-                              ws.data_ptr(), wsz, 0, torch.cuda.current_stream().cuda_stream)
-    assert rc == spz.SPZ_EUNSUPPORTED
-    # batched plans take plain containers only
-    c = _dev(oracle.compress(datagen.ar2_uint16(1000, 2, seed=1), "fire", 256, entropy=1))
-    with pytest.raises(spz.SprintzError):
-        spz.BatchDecoder([c])
+def test_entropy_segments_larger_than_the_write_image():
+    # coded segments above the write pass's 60 KiB LDS image are written in
+    # place in the container: uniform 16-bit values at D = 16 (about 128 KiB
+    # per 4096-row segment), a last segment of 3 rows, and a batch that
+    # mixes them with small ones; bytes equal to the oracle's, exact decode
+    for rows, D, S in ((8195, 16, 4096), (20000, 3, 16384)):
+        x = datagen.uniform(rows, D, np.int16, seed=rows)
+        xt = torch.from_numpy(x).cuda()
+        _say(f"entropy large segments {rows}x{D} seg_rows={S}")
+        got = spz.compress(xt, "fire", S, entropy=1).cpu().numpy().tobytes()
+        assert got == oracle.compress(x, "fire", S, entropy=1)
+        y = spz.decompress(_dev(got))
+        assert torch.equal(y.view(torch.int16), xt)
+    c0 = _dev(oracle.compress(datagen.uniform(8195, 16, np.int16, seed=5), "fire", 4096, entropy=1))
+    c1 = _dev(oracle.compress(datagen.ar2_uint16(1000, 2, seed=1), "fire", 256, entropy=1))
+    bd = spz.BatchDecoder([c0, c1])
+    bd.run()
+    torch.cuda.synchronize()
+    assert int(bd.status.abs().sum().item()) == 0
+    assert np.array_equal(bd.outs[0].cpu().numpy().view(np.int16), datagen.uniform(8195, 16, np.int16, seed=5))
+    assert np.array_equal(bd.outs[1].cpu().numpy().view(np.uint16), datagen.ar2_uint16(1000, 2, seed=1))
+    bd.close()
 
 
 def test_entropy_length_limited_codes():
