@@ -378,7 +378,7 @@ static spz_status compress_entropy(const void *d_src, uint64_t rows, uint32_t D,
     if (st != SPZ_OK) return st;
     const uint64_t data_start = align16(kHeader + 8 * (nseg + 1));
     if (nseg > 0)
-        hipLaunchKernelGGL(spz::k_huff_size, dim3((uint32_t)nseg), dim3(256), 0, stream, P, data_start, (uint32_t)nseg,
+        hipLaunchKernelGGL(spz::k_huff_size, dim3((uint32_t)nseg), dim3(64), 0, stream, P, data_start, (uint32_t)nseg,
                            info, d_status);
     hipLaunchKernelGGL(spz::k_huff_scan, dim3(1), dim3(1024), 0, stream, P, (uint32_t)nseg, data_start, info,
                        (uint8_t *)d_dst, (uint64_t)dst_cap, d_out_size, d_status);

@@ -18,8 +18,8 @@
 // u32 size[16] | the 16 sub-streams | zero pad to 16 bytes.
 //
 // Compression runs the plain encoder into a workspace container, then
-//   k_huff_size   one workgroup per segment: byte histograms (one per
-//                 sub-stream), code lengths, coded size
+//   k_huff_size   one wavefront per segment: byte histogram, code
+//                 lengths, sub-stream bits from a second pass, coded size
 //   k_huff_scan   offsets of the coded segments, container header
 //   k_huff_write  one workgroup per segment: canonical codes, every byte's
 //                 code OR-ed into an LDS image of the coded segment at its
@@ -58,70 +58,79 @@ __device__ __forceinline__ uint32_t huff_rev(uint32_t code, uint32_t len) {
 // plain: plain container (offset table at +64, data at +data_start); info:
 // kHufInfo bytes per segment: len nibbles [0,128), sub-stream bytes
 // [128,192), coded segment bytes at 192.
-__global__ __launch_bounds__(256) void k_huff_size(const uint8_t *__restrict__ plain, uint64_t data_start,
-                                                   uint32_t nseg, uint8_t *__restrict__ info,
-                                                   int32_t *__restrict__ status) {
-    __shared__ uint32_t hist[kHufSub][256];
+__global__ __launch_bounds__(64) void k_huff_size(const uint8_t *__restrict__ plain, uint64_t data_start,
+                                                  uint32_t nseg, uint8_t *__restrict__ info,
+                                                  int32_t *__restrict__ status) {
+    // One wavefront per segment, about 7 KB of LDS, so that many segments'
+    // serial merges run on a CU at once. The four byte histograms (lanes
+    // spread over them) become the merge's weights and parent links once
+    // the counts are summed.
+    __shared__ uint32_t hist[4 * 256];
     __shared__ u32x4 f4[64];                     // counts, four per entry
-    __shared__ uint32_t weight[512];
     __shared__ uint32_t order[256];
-    __shared__ uint32_t parent[512];
     __shared__ uint32_t len[256];
     __shared__ uint32_t sub_bits[kHufSub];
     __shared__ uint32_t nsym, maxlen;
+    uint32_t *const weight = hist;               // [512], after the counts are summed
+    uint32_t *const parent = hist + 512;         // [512]
     const uint32_t t = threadIdx.x, s = blockIdx.x;
     if (s >= nseg) return;
     const uint64_t a = gld64(plain + 64 + 8ull * s), b = gld64(plain + 64 + 8ull * (s + 1));
     const uint8_t *seg = plain + data_start + a;
     const uint32_t n = (uint32_t)(b - a);
     const uint32_t m16 = n / kHufSub;
-    for (uint32_t k = t; k < kHufSub * 256; k += 256) (&hist[0][0])[k] = 0;
+    for (uint32_t k = t; k < 4 * 256; k += 64) hist[k] = 0;
     if (t < kHufSub) sub_bits[t] = 0;
-    __syncthreads();
-    // byte histograms per sub-stream (16-byte loads)
-    for (uint32_t q = t; q < n / 16; q += 256) {
-        const u32x4 v = gld128(seg + 16 * q);
-        const uint32_t wds[4] = {v.x, v.y, v.z, v.w};
-        uint32_t pos = 16 * q, k = pos / m16;
+    wave_sync();
+    // byte histogram (16-byte loads)
+    {
+        uint32_t *const h = hist + 256 * (t & 3);
+        for (uint32_t q = t; q < n / 16; q += 64) {
+            const u32x4 v = gld128(seg + 16 * q);
+            const uint32_t wds[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int i = 0; i < 16; ++i, ++pos) {
-            while (pos >= (k + 1) * m16) ++k;
-            atomicAdd(&hist[k][(wds[i >> 2] >> (8 * (i & 3))) & 0xFFu], 1u);
+            for (int i = 0; i < 16; ++i) atomicAdd(&h[(wds[i >> 2] >> (8 * (i & 3))) & 0xFFu], 1u);
         }
     }
-    __syncthreads();
-    uint32_t c = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < kHufSub; ++k) c += hist[k][t];
+    wave_sync();
     uint32_t *const f = reinterpret_cast<uint32_t *>(f4);
-    f[t] = c;
+#pragma unroll
+    for (uint32_t r = 0; r < 4; ++r) {
+        const uint32_t v = t + 64 * r;
+        f[v] = hist[v] + hist[256 + v] + hist[512 + v] + hist[768 + v];
+    }
+    wave_sync();
     // code lengths: two-queue construction, repeated on halved counts while
-    // a length exceeds the limit
+    // a length exceeds the limit; lane t holds values t, t+64, t+128, t+192
+    uint32_t fv[4], rank[4], lv[4];
     for (;;) {
         if (t == 0) { nsym = 0; maxlen = 0; }
-        __syncthreads();
-        const uint32_t fv = f[t];
-        uint32_t rank = 0;
-        if (fv) {
-            // rank by (count, value): 16-byte reads, 8 in flight
-#pragma unroll 8
-            for (uint32_t u4 = 0; u4 < 64; ++u4) {
-                const u32x4 v = f4[u4];
-                const uint32_t fu[4] = {v.x, v.y, v.z, v.w};
+        wave_sync();
 #pragma unroll
-                for (uint32_t q = 0; q < 4; ++q) {
-                    const uint32_t u = 4 * u4 + q;
-                    rank += (fu[q] != 0 && (fu[q] < fv || (fu[q] == fv && u < t))) ? 1u : 0u;
+        for (uint32_t r = 0; r < 4; ++r) { fv[r] = f[t + 64 * r]; rank[r] = 0; }
+        // rank by (count, value): 16-byte reads of all counts
+        for (uint32_t u4 = 0; u4 < 64; ++u4) {
+            const u32x4 c = f4[u4];
+            const uint32_t fu[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q) {
+                const uint32_t u = 4 * u4 + q;
+#pragma unroll
+                for (uint32_t r = 0; r < 4; ++r) {
+                    const uint32_t v = t + 64 * r;
+                    rank[r] += (fu[q] != 0 && (fu[q] < fv[r] || (fu[q] == fv[r] && u < v))) ? 1u : 0u;
                 }
             }
-            order[rank] = t;
-            atomicAdd(&nsym, 1u);
         }
-        __syncthreads();
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r)
+            if (fv[r]) { order[rank[r]] = t + 64 * r; atomicAdd(&nsym, 1u); }
+        wave_sync();
         const uint32_t m = nsym;
         if (m == 1) {
-            len[t] = fv ? 1u : 0u;
-            __syncthreads();
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r) { lv[r] = fv[r] ? 1u : 0u; len[t + 64 * r] = lv[r]; }
+            wave_sync();
             break;
         }
         if (t == 0) {
@@ -150,29 +159,50 @@ __global__ __launch_bounds__(256) void k_huff_size(const uint8_t *__restrict__ p
                 ++next;
             }
         }
-        __syncthreads();
-        uint32_t d = 0;
-        if (fv) {
-            const uint32_t root = 2 * m - 2;
-            for (uint32_t q = rank; q != root; q = parent[q]) ++d;
-            atomicMax(&maxlen, d);
+        wave_sync();
+        uint32_t dmax = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
+            uint32_t d = 0;
+            if (fv[r]) {
+                const uint32_t root = 2 * m - 2;
+                for (uint32_t q = rank[r]; q != root; q = parent[q]) ++d;
+            }
+            lv[r] = d;
+            len[t + 64 * r] = d;
+            dmax = max(dmax, d);
         }
-        len[t] = d;
-        __syncthreads();
+        atomicMax(&maxlen, dmax);
+        wave_sync();
         if (maxlen <= kHufMaxLen) break;
-        f[t] = (fv + 1) >> 1;
-        __syncthreads();
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) f[t + 64 * r] = (fv[r] + 1) >> 1;
+        wave_sync();
     }
-    // bits of every sub-stream: sum over values of count * length
-    {
-        const uint32_t k = t >> 4, v0 = (t & 15) * 16;
-        uint32_t bits = 0;
-        for (uint32_t v = v0; v < v0 + 16; ++v) bits += hist[k][v] * len[v];
-        atomicAdd(&sub_bits[k], bits);
+    // bits of every sub-stream: a second pass over the segment's bytes
+    // (sub-stream k holds bytes [k m16, (k+1) m16))
+    for (uint32_t q = t; q < n / 16; q += 64) {
+        const u32x4 v = gld128(seg + 16 * q);
+        const uint32_t wds[4] = {v.x, v.y, v.z, v.w};
+        uint32_t pos = 16 * q, k = pos / m16, bits = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i, ++pos) {
+            if (pos >= (k + 1) * m16) {
+                atomicAdd(&sub_bits[k], bits);
+                bits = 0;
+                while (pos >= (k + 1) * m16) ++k;
+            }
+            bits += len[(wds[i >> 2] >> (8 * (i & 3))) & 0xFFu];
+        }
+        atomicAdd(&sub_bits[min(k, kHufSub - 1)], bits);
     }
-    __syncthreads();
+    wave_sync();
     uint8_t *rec = info + (uint64_t)s * kHufInfo;
-    if (t < 128) rec[t] = (uint8_t)(len[2 * t] | (len[2 * t + 1] << 4));
+#pragma unroll
+    for (uint32_t r = 0; r < 2; ++r) {
+        const uint32_t b2 = t + 64 * r;   // byte of the nibble table: values 2 b2 and 2 b2 + 1
+        rec[b2] = (uint8_t)(len[2 * b2] | (len[2 * b2 + 1] << 4));
+    }
     if (t < kHufSub) reinterpret_cast<uint32_t *>(rec + 128)[t] = (sub_bits[t] + 7) >> 3;
     if (t == 0) {
         uint32_t tot = kHufFixed;
