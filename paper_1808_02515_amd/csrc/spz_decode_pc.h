@@ -607,18 +607,20 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
 
 // Pipelined form: decodes the segments whose state the parser puts in SEG
 // (nchunks chunks of kPcChunkBlocks blocks). Called by all threads of the
-// workgroup. The
-// wavefronts form a three-stage pipeline over the chunks, one barrier per
-// step: at step t the parser (wave 0) stores chunk t's staged windows, parses
-// chunk t and issues the loads of chunk t+1's windows; the NP unpacking waves
-// unpack chunk t-1; the consumer runs the recurrence of chunk t-2. Staging
-// windows, records and error buffers are double buffered by chunk parity.
+// workgroup. The wavefronts form a four-stage pipeline over the chunks, one
+// barrier per step: at step t the parser (wave 0) stores chunk t's staged
+// windows, parses chunk t and issues the loads of chunk t+1's windows; the NP
+// unpacking waves store chunk t-3's rows to global memory and unpack chunk
+// t-1; the consumer runs the recurrence of chunk t-2 into a row image.
+// Staging windows, records, error buffers and row images are double buffered
+// by chunk parity. The consumer's recurrence is the longest stage, so it does
+// nothing else.
 template <int W, bool FIRE, int D, int NP, int NC, typename Init>
 __device__ __forceinline__ void pc_decode_group_pipe(uint32_t nchunks, Init init, int32_t *__restrict__ status) {
     constexpr int CB = kPcChunkBlocks;
     using G = PcGeom<W, D, CB, NP, NC>;
     constexpr uint32_t HB = G::HB, WB = G::WB, SPW = G::SPW, SPP = G::SPP, HU = G::HU, NU = G::NU;
-    constexpr uint32_t ZSTR = G::ZSTR, OSEG = G::OSEG;
+    constexpr uint32_t ZSTR = G::ZSTR;
     constexpr bool ROW = D * W > 32;   // row-major payloads (reading R13)
     static_assert(SPP * NP == SPW && SPP >= 1 && SPP <= 64 && SPW <= 64 && CB <= 16 && G::DP <= 16, "geometry");
     static_assert(!G::ROW || G::IL >= 2, "row-major items hold whole column groups");
@@ -626,25 +628,33 @@ __device__ __forceinline__ void pc_decode_group_pipe(uint32_t nchunks, Init init
     // One LDS arena, staging windows first: field addresses then need no base.
     constexpr uint32_t SLOT = SPW * NU * 16;                       // one chunk's windows
     constexpr uint32_t O_ZB = 2 * SLOT;                            // [parity][segment][header | payload window]
-    constexpr uint32_t O_OUT = O_ZB + 2 * G::CHAINS * ZSTR;        // [parity][chain] errors of a chunk
-    // [segment] output rows of a chunk, plus a discard image for consumer
-    // lanes without a column chain (D not dividing the wavefront)
-    constexpr uint32_t NOUT = G::USED < G::CHAINS ? SPW + 1 : SPW;
-    constexpr uint32_t O_REC = (O_OUT + NOUT * OSEG + 15) & ~15u;
+    // [parity][chain] errors of a chunk. Once the consumer holds a chunk's
+    // errors in registers, it writes the chunk's output rows over them: the
+    // row image of segment s lies inside the error buffers of s's own D
+    // chains (which hold 16 * D bytes more than its rows), shifted by OST * s
+    // bytes so that the images of different segments start in different LDS
+    // banks. The unpacking wave that owns s stores that image in the next
+    // step, before it unpacks its next chunk into the same buffers.
+    constexpr uint32_t ZPAR = G::CHAINS * ZSTR;                     // one parity's error buffers
+    constexpr uint32_t ROWB = CB * 8 * D * WB;                       // one segment's rows of a chunk
+    constexpr uint32_t OST = (SPW - 1) * ((D * WB + 15) & ~15u) <= 16 * D ? (D * WB + 15) & ~15u : 16u;
+    static_assert(ZSTR == CB * 8 * WB + 16 && (SPW - 1) * OST <= 16 * D && (D * ZSTR) % 16 == 0,
+                  "a segment's row image fits its chains' error buffers");
+    constexpr uint32_t O_DIS = O_ZB + 2 * ZPAR;                     // rows of consumer lanes without a chain
+    constexpr uint32_t O_REC = O_DIS + (G::USED < G::CHAINS ? ROWB : 0u);
     constexpr uint32_t O_BM = O_REC + 2 * SPW * CB * 16;           // [parity][segment][candidate]: codes lo, hi, payload bit, bits per row
     constexpr uint32_t O_SEG = (O_BM + 2 * SPW * CB * 4 + 15) & ~15u;  // [parity][segment][block]: candidate or kPcZero
     constexpr uint32_t O_END = O_SEG + SPW * (uint32_t)sizeof(PcSeg);
     __shared__ u32x4 ARENA[O_END / 16];
     u32x4 *const STG = ARENA;
     u32x4 *const ZB4 = reinterpret_cast<u32x4 *>(reinterpret_cast<uint8_t *>(ARENA) + O_ZB);
-    uint32_t *const OUTW = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(ARENA) + O_OUT);
     u32x4 *const REC = reinterpret_cast<u32x4 *>(reinterpret_cast<uint8_t *>(ARENA) + O_REC);
     uint32_t *const BM = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(ARENA) + O_BM);
     PcSeg *const SEG = reinterpret_cast<PcSeg *>(reinterpret_cast<uint8_t *>(ARENA) + O_SEG);
     static_assert(O_END % 16 == 0 && sizeof(PcSeg) % 16 == 0, "arena layout");
     const uint32_t *const stgw = reinterpret_cast<const uint32_t *>(STG);
     uint8_t *const zb = reinterpret_cast<uint8_t *>(ZB4);
-    uint8_t *const outb = reinterpret_cast<uint8_t *>(OUTW);
+    uint8_t *const arena = reinterpret_cast<uint8_t *>(ARENA);
 
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid >> 6, lane = tid & 63;
@@ -695,15 +705,14 @@ __device__ __forceinline__ void pc_decode_group_pipe(uint32_t nchunks, Init init
     const uint32_t cs = c_on ? chain / D : SPW, cj = c_on ? chain % D : 0u;
     uint32_t x = 0;
     int32_t delta = 0, acc = 0;
-    uint32_t c_sh = 0, c_nb = 0;
+    uint32_t c_sh = 0;
     int32_t c_lo = 0, c_hi = 0;
-    uint8_t *c_dst = nullptr;
     if (c_on) {
         const PcSeg &q = SEG[cs];
-        c_sh = q.sh; c_lo = q.acc_lo; c_hi = q.acc_hi; c_dst = q.dst; c_nb = q.nrow >> 3;
+        c_sh = q.sh; c_lo = q.acc_lo; c_hi = q.acc_hi;
     }
 
-    for (uint32_t t = 0; t < nchunks + 2; ++t) {
+    for (uint32_t t = 0; t < nchunks + 3; ++t) {
         if (parser && t < nchunks) {
             const uint32_t c = t;
             stage_commit(c);
@@ -769,7 +778,38 @@ __device__ __forceinline__ void pc_decode_group_pipe(uint32_t nchunks, Init init
             wave_sync();
             // ---- the next chunk's windows: loads in flight over the step ------
             if (c + 1 < nchunks) stage_issue();
-        } else if (unpacker && t >= 1 && t <= nchunks) {
+        } else if (unpacker) {
+          if (t >= 3) {
+            // ---- output: this wave's segments' rows of chunk t-3 ----------------
+            // lanes = 16-byte units of the segments' row images
+            const uint32_t c = t - 3;
+            constexpr uint32_t NUS = CB * 8 * D * WB / 16;   // units of one segment's chunk
+            constexpr uint32_t OPASS = (SPP * NUS + 63) / 64;
+            const uint8_t *const img = zb + (c & 1) * ZPAR;
+#pragma unroll
+            for (uint32_t op = 0; op < OPASS; ++op) {
+                const uint32_t u = lane + 64 * op;
+                const uint32_t s = ps0 + min(u / NUS, SPP - 1), lo = 16 * (u % NUS);
+                const PcSeg &sg = SEG[s];
+                const uint32_t nbk = sg.nrow >> 3;
+                const uint32_t bic = c * CB < nbk ? min((uint32_t)CB, nbk - c * CB) : 0u;
+                // rows of the chunk in whole blocks (none for a segment that
+                // failed its checks: nrow is 0 there); units past them, and
+                // lanes past the wave's units, store nothing
+                const uint32_t valid = u < SPP * NUS ? bic * 8 * D * WB : 0u;
+                uint8_t *const gp = sg.dst + (size_t)c * CB * 8 * D * WB;
+                const uint8_t *const si = img + s * (D * ZSTR + OST) + lo;
+                if (lo + 16 <= valid) {
+                    gst128(gp + lo, *reinterpret_cast<const u32x4 *>(si));
+                } else if (lo + 8 == valid) {
+                    const uint32_t *q = reinterpret_cast<const uint32_t *>(si);
+                    gst32(gp + lo, q[0]);
+                    gst32(gp + lo + 4, q[1]);
+                }
+            }
+            wave_sync();   // every lane has read the images before any unpacks over them
+          }
+          if (t >= 1 && t <= nchunks) {
             const uint32_t c = t - 1;
             // ---- unpack ------------------------------------------------------
             // One aligned two-dword LDS read and a funnel shift give 32
@@ -870,14 +910,16 @@ __device__ __forceinline__ void pc_decode_group_pipe(uint32_t nchunks, Init init
                     }
                 }
             }
-        } else if (consumer && t >= 2) {
+          }
+        } else if (consumer && t >= 2 && t <= nchunks + 1) {
             const uint32_t c = t - 2;
             // ---- recurrence: lane = column chain ------------------------------
             const uint8_t *const zc = zb + (c & 1) * G::CHAINS * ZSTR + chain * ZSTR;
-            const uint32_t obase = cs * OSEG + cj * WB;
+            const uint32_t obase = c_on ? O_ZB + (c & 1) * ZPAR + cs * (D * ZSTR + OST) + cj * WB : O_DIS;
             const uint32_t sh = c_sh;
             const int32_t acc_lo = c_lo, acc_hi = c_hi;
-            // the whole chunk's errors first: one LDS wait per chunk
+            // the whole chunk's errors first: one LDS wait per chunk, and every
+            // lane holds its errors before any writes rows over them
             uint32_t evs[CB][4];
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
@@ -890,6 +932,7 @@ __device__ __forceinline__ void pc_decode_group_pipe(uint32_t nchunks, Init init
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
+            wave_sync();
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
                 const uint32_t *const ev = evs[b];
@@ -917,34 +960,10 @@ __device__ __forceinline__ void pc_decode_group_pipe(uint32_t nchunks, Init init
                         x += (uint32_t)e;
                     }
                     const uint32_t o = obase + (uint32_t)((8 * b + i) * D * WB);
-                    if (WB == 1) outb[o] = (uint8_t)x;
-                    else *reinterpret_cast<uint16_t *>(outb + o) = (uint16_t)x;
+                    if (WB == 1) arena[o] = (uint8_t)x;
+                    else *reinterpret_cast<uint16_t *>(arena + o) = (uint16_t)x;
                 }
                 if (FIRE) acc = min(max(acc + grad, acc_lo), acc_hi);
-            }
-            wave_sync();
-            // ---- output: each segment's rows of this chunk ---------------------
-            const uint32_t bic = c * CB < c_nb ? min((uint32_t)CB, c_nb - c * CB) : 0u;
-            const uint32_t valid = bic * 8 * D * WB;
-            // (lanes without a column chain have no rows: valid is 0 there)
-            uint8_t *const gp = c_on ? c_dst + (size_t)c * CB * 8 * D * WB : c_dst;
-#pragma unroll
-            for (uint32_t u = 0; u < G::UPL; ++u) {
-                const uint32_t lo = 16 * (cj + u * D);
-                if (lo + 16 <= valid) {
-                    u32x4 v;
-                    if (G::WIDE) {
-                        v = *reinterpret_cast<const u32x4 *>(outb + cs * OSEG + lo);
-                    } else {
-                        const uint32_t *p = reinterpret_cast<const uint32_t *>(outb + cs * OSEG + lo);
-                        v.x = p[0]; v.y = p[1]; v.z = p[2]; v.w = p[3];
-                    }
-                    gst128(gp + lo, v);
-                } else if (lo + 8 == valid) {
-                    const uint32_t *p = reinterpret_cast<const uint32_t *>(outb + cs * OSEG + lo);
-                    gst32(gp + lo, p[0]);
-                    gst32(gp + lo + 4, p[1]);
-                }
             }
         }
         __syncthreads();
