@@ -111,7 +111,9 @@ def test_compress_batch_equals_oracle():
 def test_compress_batch_many_small_and_some_large():
     # hundreds of short series of one class fill workgroups together with
     # large ones; two classes of 16-bit FIRE series
-    cases = []
+    # (first, with the full workspace) 5,001 segments: a series' offset scan
+    # takes its sizes in rounds of 2,048
+    cases = [(datagen.ar2_uint16(40_000 + 5, 4, seed=900), "delta", 8, 0)]
     for k in range(300):
         cases.append((datagen.ar2_uint16(int(1000 + 37 * k), 8, seed=700 + k), "fire", 1024, 0))
     for k in range(4):

@@ -90,6 +90,13 @@ def test_ar2_uint16_full_size(f):
     _check(x, f, 1024, label="ar2 full")
 
 
+@pytest.mark.parametrize("f", ["delta", "fire"])
+def test_offset_scan_over_several_rounds(f):
+    # 10,001 segments: the offset scan takes its sizes in rounds of 8,192
+    x = datagen.ar2_uint16(80_000 + 3, 2, seed=5)
+    _check(x, f, 8, label="scan rounds")
+
+
 def test_random_corpus():
     rng = np.random.default_rng(2024)
     for k in range(120):
