@@ -273,24 +273,34 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
     // One LDS arena, staging windows first: field addresses then need no base.
     constexpr uint32_t O_ZB = SPW * NU * 16;                       // [segment][header window | payload window]
     constexpr uint32_t O_OUT = O_ZB + 2 * G::CHAINS * ZSTR;        // [buffer][chain] errors of a chunk
-    // [segment] output rows of a chunk, plus a discard image for consumer
-    // lanes without a column chain (D not dividing the wavefront)
-    constexpr uint32_t NOUT = G::USED < G::CHAINS ? SPW + 1 : SPW;
-    constexpr uint32_t O_REC = (O_OUT + NOUT * OSEG + 15) & ~15u;
+    // Output rows of a chunk. With at most D + 1 segments per workgroup
+    // (D >= 7), the consumer writes them over the errors it has just read:
+    // the row image of segment s lies inside the error buffers of its own D
+    // chains (16 * D bytes more than its rows), shifted by OST * s bytes so
+    // that the images start in different LDS banks. Otherwise a row image
+    // [segment] of its own. Consumer lanes without a column chain (D not
+    // dividing the wavefront) write a discard image.
+    constexpr uint32_t ZPAR = G::CHAINS * ZSTR, ROWB = CB * 8 * D * WB;
+    constexpr bool REUSE = SPW <= D + 1;
+    constexpr uint32_t OST = (SPW - 1) * ((D * WB + 15) & ~15u) <= 16 * D ? (D * WB + 15) & ~15u : 16u;
+    static_assert(!REUSE || (ZSTR == CB * 8 * WB + 16 && (SPW - 1) * OST <= 16 * D && (D * ZSTR) % 16 == 0),
+                  "a segment's row image fits its chains' error buffers");
+    constexpr uint32_t NOUT = REUSE ? 0u : G::USED < G::CHAINS ? SPW + 1 : SPW;
+    constexpr uint32_t O_DIS = O_OUT + NOUT * OSEG;                   // discard image (REUSE)
+    constexpr uint32_t O_REC = (O_DIS + (REUSE && G::USED < G::CHAINS ? ROWB : 0u) + 15) & ~15u;
     constexpr uint32_t O_BM = O_REC + SPW * CB * 16;               // [segment][candidate]: codes lo, hi, payload bit, bits per row
     constexpr uint32_t O_SEG = (O_BM + SPW * CB * 4 + 15) & ~15u;  // [segment][block]: candidate or kPcZero
     constexpr uint32_t O_END = O_SEG + SPW * (uint32_t)sizeof(PcSeg);
     __shared__ u32x4 ARENA[O_END / 16];
     u32x4 *const STG = ARENA;
     u32x4 *const ZB4 = reinterpret_cast<u32x4 *>(reinterpret_cast<uint8_t *>(ARENA) + O_ZB);
-    uint32_t *const OUTW = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(ARENA) + O_OUT);
     u32x4 *const REC = reinterpret_cast<u32x4 *>(reinterpret_cast<uint8_t *>(ARENA) + O_REC);
     uint32_t *const BM = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(ARENA) + O_BM);
     PcSeg *const SEG = reinterpret_cast<PcSeg *>(reinterpret_cast<uint8_t *>(ARENA) + O_SEG);
     static_assert(O_END % 16 == 0 && sizeof(PcSeg) % 16 == 0, "arena layout");
     const uint32_t *const stgw = reinterpret_cast<const uint32_t *>(STG);
     uint8_t *const zb = reinterpret_cast<uint8_t *>(ZB4);
-    uint8_t *const outb = reinterpret_cast<uint8_t *>(OUTW);
+    uint8_t *const arena = reinterpret_cast<uint8_t *>(ARENA);
 
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid >> 6, lane = tid & 63;
@@ -512,7 +522,9 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
             const uint32_t c = t - 1;
             // ---- recurrence: lane = column chain ------------------------------
             const uint8_t *const zc = zb + (c & 1) * G::CHAINS * ZSTR + chain * ZSTR;
-            const uint32_t obase = cs * OSEG + cj * WB;
+            // row image of segment cs (byte offset in the arena)
+            const uint32_t ibase = REUSE ? O_ZB + (c & 1) * ZPAR + cs * (D * ZSTR + OST) : O_OUT + cs * OSEG;
+            const uint32_t obase = (REUSE && !c_on ? O_DIS : ibase) + cj * WB;
             const uint32_t sh = c_sh;
             const int32_t acc_lo = c_lo, acc_hi = c_hi;
             // the whole chunk's errors first: one LDS wait per chunk
@@ -528,6 +540,7 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
+            if (REUSE) wave_sync();   // every lane holds its errors before any writes rows over them
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
                 const uint32_t *const ev = evs[b];
@@ -555,8 +568,8 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
                         x += (uint32_t)e;
                     }
                     const uint32_t o = obase + (uint32_t)((8 * b + i) * D * WB);
-                    if (WB == 1) outb[o] = (uint8_t)x;
-                    else *reinterpret_cast<uint16_t *>(outb + o) = (uint16_t)x;
+                    if (WB == 1) arena[o] = (uint8_t)x;
+                    else *reinterpret_cast<uint16_t *>(arena + o) = (uint16_t)x;
                 }
                 if (FIRE) acc = min(max(acc + grad, acc_lo), acc_hi);
             }
@@ -564,22 +577,24 @@ __device__ __forceinline__ void pc_decode_group(uint32_t nchunks, Init init, int
             // ---- output: each segment's rows of this chunk ---------------------
             const uint32_t bic = c * CB < c_nb ? min((uint32_t)CB, c_nb - c * CB) : 0u;
             const uint32_t valid = bic * 8 * D * WB;
-            // (lanes without a column chain have no rows: valid is 0 there)
-            uint8_t *const gp = c_on ? c_dst + (size_t)c * CB * 8 * D * WB : c_dst;
+            // (lanes without a column chain, and segments without rows such as
+            // a batch's empty work-list entries, whose dst is null, have valid
+            // 0 and store nothing)
+            uint8_t *const gp = valid ? c_dst + (size_t)c * CB * 8 * D * WB : c_dst;
 #pragma unroll
             for (uint32_t u = 0; u < G::UPL; ++u) {
                 const uint32_t lo = 16 * (cj + u * D);
                 if (lo + 16 <= valid) {
                     u32x4 v;
-                    if (G::WIDE) {
-                        v = *reinterpret_cast<const u32x4 *>(outb + cs * OSEG + lo);
+                    if (REUSE || G::WIDE) {
+                        v = *reinterpret_cast<const u32x4 *>(arena + ibase + lo);
                     } else {
-                        const uint32_t *p = reinterpret_cast<const uint32_t *>(outb + cs * OSEG + lo);
+                        const uint32_t *p = reinterpret_cast<const uint32_t *>(arena + ibase + lo);
                         v.x = p[0]; v.y = p[1]; v.z = p[2]; v.w = p[3];
                     }
                     gst128(gp + lo, v);
                 } else if (lo + 8 == valid) {
-                    const uint32_t *p = reinterpret_cast<const uint32_t *>(outb + cs * OSEG + lo);
+                    const uint32_t *p = reinterpret_cast<const uint32_t *>(arena + ibase + lo);
                     gst32(gp + lo, p[0]);
                     gst32(gp + lo + 4, p[1]);
                 }

@@ -3,14 +3,17 @@
 // coroutine scheduler of emu_sched.h, with bounds-checked global accesses
 // (spz_device_ops.h of this directory) under AddressSanitizer.
 //
-//   emu_decode <container> <rows out>
+//   emu_decode <container> <rows out> [batch]
 // Prints "status=<device status word> violations=<out-of-bounds accesses>
 // blocks=<workgroups>" and writes the decoded rows. The geometry follows the
-// library's host code: the producer/consumer decoder for whole-segment
-// header groups with D <= 16 (16-byte aligned rows), the walker otherwise.
+// library's host code: the producer/consumer or pipelined decoder for
+// whole-segment header groups with D <= 16 (16-byte aligned rows), the walker
+// otherwise. With "batch", such containers go through the batched kernel
+// instead (a one-stream batch: the producer/consumer form at every D).
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <vector>
 
@@ -39,6 +42,34 @@ static void run_pc(const uint8_t *src, const spz::Geom &g, uint8_t *dst, int32_t
     *blocks = grid;
 }
 
+// The batched kernel on a batch of this one container: work-list groups of
+// SPW segments (the last padded with empty entries), one persistent
+// workgroup per eight groups.
+template <int W, bool FIRE, int D>
+static void run_pc_batch(const uint8_t *src, const spz::Geom &g, uint8_t *dst, int32_t *status, uint32_t *blocks) {
+    constexpr uint32_t NP = spz::kPcProducers, NC = spz::kPcConsumers;
+    const uint32_t spw = spz::pc_spw(D, NP, NC);
+    const uint32_t ngroups = (g.nseg + spw - 1) / spw;
+    spz::PcStream st;
+    memset(&st, 0, sizeof st);
+    st.src = src; st.dst = dst; st.data_start = g.data_start; st.data_bytes = g.data_bytes; st.rows = g.rows;
+    st.nseg = g.nseg; st.S = g.S; st.sh = g.sh; st.acc_lo = g.acc_lo; st.acc_hi = g.acc_hi;
+    std::vector<uint64_t> entries((size_t)ngroups * spw, ~0ull);
+    for (uint32_t q = 0; q < g.nseg; ++q) entries[q] = q;   // stream 0
+    std::vector<uint32_t> group_s(ngroups, g.S);
+    uint32_t queue = 0;
+    const uint32_t grid = (ngroups + 7) / 8;
+    for (uint32_t b = 0; b < grid; ++b) {
+        emu::dim3e bid, bdim;
+        bid.x = b;
+        bdim.x = spz::pc_threads(NP, NC);
+        emu::run_block(bid, bdim, [&] {
+            spz::k_decode_pc_batch<W, FIRE, D, NP, NC>(&st, entries.data(), group_s.data(), ngroups, &queue, status);
+        });
+    }
+    *blocks = grid;
+}
+
 template <int W, bool FIRE, bool COL>
 static void run_walker(const uint8_t *src, const spz::Geom &g, uint8_t *dst, int32_t *status, uint32_t *blocks) {
     const uint32_t lg = g.dp_log2 < 6 ? g.dp_log2 : 6u;
@@ -56,24 +87,26 @@ static void run_walker(const uint8_t *src, const spz::Geom &g, uint8_t *dst, int
 }
 
 template <int W, bool FIRE>
-static bool dispatch_pc(uint32_t D, const uint8_t *src, const spz::Geom &g, uint8_t *dst, int32_t *st, uint32_t *nb) {
+static bool dispatch_pc(uint32_t D, const uint8_t *src, const spz::Geom &g, uint8_t *dst, int32_t *st, uint32_t *nb,
+                        bool batch) {
+#define SPZ_EMU_D(D_)                                                 \
+    case D_:                                                          \
+        if (batch) run_pc_batch<W, FIRE, D_>(src, g, dst, st, nb);    \
+        else run_pc<W, FIRE, D_>(src, g, dst, st, nb);                \
+        return true;
     switch (D) {
-        case 1: run_pc<W, FIRE, 1>(src, g, dst, st, nb); return true;
-        case 2: run_pc<W, FIRE, 2>(src, g, dst, st, nb); return true;
-        case 3: run_pc<W, FIRE, 3>(src, g, dst, st, nb); return true;
-        case 4: run_pc<W, FIRE, 4>(src, g, dst, st, nb); return true;
-        case 5: run_pc<W, FIRE, 5>(src, g, dst, st, nb); return true;
-        case 8: run_pc<W, FIRE, 8>(src, g, dst, st, nb); return true;
-        case 16: run_pc<W, FIRE, 16>(src, g, dst, st, nb); return true;
+        SPZ_EMU_D(1) SPZ_EMU_D(2) SPZ_EMU_D(3) SPZ_EMU_D(4) SPZ_EMU_D(5) SPZ_EMU_D(8) SPZ_EMU_D(16)
         default: return false;
     }
+#undef SPZ_EMU_D
 }
 
 int main(int argc, char **argv) {
-    if (argc != 3) {
-        fprintf(stderr, "usage: %s <container> <rows out>\n", argv[0]);
+    if (argc != 3 && !(argc == 4 && strcmp(argv[3], "batch") == 0)) {
+        fprintf(stderr, "usage: %s <container> <rows out> [batch]\n", argv[0]);
         return 2;
     }
+    const bool batch = argc == 4;
     FILE *f = fopen(argv[1], "rb");
     if (!f) return 2;
     std::vector<uint8_t> buf;
@@ -117,10 +150,10 @@ int main(int argc, char **argv) {
     const bool col = (uint64_t)D * w <= 32;
     bool ran = false;
     if (nseg > 0 && pc) {
-        if (w == 8) ran = forecaster ? dispatch_pc<8, true>(D, src, g, dst, &status, &blocks)
-                                     : dispatch_pc<8, false>(D, src, g, dst, &status, &blocks);
-        else ran = forecaster ? dispatch_pc<16, true>(D, src, g, dst, &status, &blocks)
-                              : dispatch_pc<16, false>(D, src, g, dst, &status, &blocks);
+        if (w == 8) ran = forecaster ? dispatch_pc<8, true>(D, src, g, dst, &status, &blocks, batch)
+                                     : dispatch_pc<8, false>(D, src, g, dst, &status, &blocks, batch);
+        else ran = forecaster ? dispatch_pc<16, true>(D, src, g, dst, &status, &blocks, batch)
+                              : dispatch_pc<16, false>(D, src, g, dst, &status, &blocks, batch);
     } else if (nseg > 0) {
         ran = true;
         if (w == 8) {

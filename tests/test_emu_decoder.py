@@ -45,12 +45,13 @@ def harness(tmp_path_factory):
     return out
 
 
-def _decode(harness, blob: bytes, tmp, shape, dtype):
+def _decode(harness, blob: bytes, tmp, shape, dtype, batch=False):
     c, o = os.path.join(tmp, "c.bin"), os.path.join(tmp, "o.bin")
     with open(c, "wb") as fh:
         fh.write(blob)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
-    r = subprocess.run([harness, c, o], capture_output=True, text=True, timeout=600, env=env)
+    r = subprocess.run([harness, c, o] + (["batch"] if batch else []), capture_output=True, text=True, timeout=600,
+                       env=env)
     assert r.returncode == 0, r.stderr[-2000:]
     assert "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr, r.stderr[-2000:]
     fields = dict(kv.split("=") for kv in r.stdout.split())
@@ -77,9 +78,12 @@ def test_corpus_decodes_exactly_in_bounds(harness, tmp_path):
         f = ["fire", "delta"][k % 3 % 2]
         S = int(rng.choice([8, 64, 256, 1024]))
         G = [0, 0, 2][k % 3]
-        st, viol, y = _decode(harness, oracle.compress(x, f, S, G), str(tmp_path), x.shape, x.dtype)
-        assert (st, viol) == (0, 0), (k, D, rows, dt, f, S, G)
-        assert np.array_equal(y, x), (k, D, rows, dt, f, S, G)
+        blob = oracle.compress(x, f, S, G)
+        # D <= 16 without header groups also through the batched kernel
+        for batch in (False, True) if D <= 16 and G == 0 else (False,):
+            st, viol, y = _decode(harness, blob, str(tmp_path), x.shape, x.dtype, batch)
+            assert (st, viol) == (0, 0), (k, D, rows, dt, f, S, G, batch)
+            assert np.array_equal(y, x), (k, D, rows, dt, f, S, G, batch)
 
 
 def test_corrupted_containers_stay_in_bounds(harness, tmp_path):
@@ -98,4 +102,7 @@ def test_corrupted_containers_stay_in_bounds(harness, tmp_path):
         st, viol, _ = _decode(harness, bytes(blob), str(tmp_path), x.shape, x.dtype)
         assert viol == 0, k
         flagged += st != 0
+        if D <= 16:
+            _, viol, _ = _decode(harness, bytes(blob), str(tmp_path), x.shape, x.dtype, True)
+            assert viol == 0, (k, "batch")
     assert flagged > 0
