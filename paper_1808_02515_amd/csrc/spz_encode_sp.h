@@ -583,38 +583,49 @@ __global__ __launch_bounds__(es_threads(D)) void k_encode_sp_batch(const EsStrea
     }
 }
 
-// Offset table and container header from the segment sizes (one workgroup):
-// each thread sums a contiguous run of segments, one block scan, then the
-// table entries of its run.
+// Offset table and container header from the segment sizes (one workgroup),
+// in rounds of R sizes per thread: a thread loads a contiguous run of R sizes
+// at once (one memory latency per round, not one per size), one block scan,
+// then the table entries of its run; a carry links the rounds.
 __device__ __forceinline__ void es_scan_body(const u32x4 *__restrict__ info, uint32_t n, uint64_t rows, uint32_t D,
                                              uint32_t S, uint32_t G, uint64_t data_start, uint64_t cap, uint32_t w,
                                              uint32_t dtype, uint32_t forecaster, uint32_t learn_shift,
                                              uint8_t *__restrict__ dst, uint64_t *__restrict__ out_size,
                                              int32_t *__restrict__ status) {
+    constexpr uint32_t R = 8;
     __shared__ uint64_t wsum[16];
     const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6, nt = blockDim.x, nw = nt >> 6;
-    const uint32_t per = (n + nt - 1) / nt;
-    const uint32_t k0 = min(n, t * per), k1 = min(n, k0 + per);
-    uint64_t mine = 0;
-    for (uint32_t k = k0; k < k1; ++k) mine += info[k].x;
-    uint64_t incl = mine;
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-        const uint64_t o = (uint64_t)__shfl_up((unsigned long long)incl, d, 64);
-        if (lane >= d) incl += o;
-    }
-    if (lane == 63) wsum[wv] = incl;
-    __syncthreads();
-    uint64_t before = 0, total = 0;
-    for (uint32_t q = 0; q < nw; ++q) {
-        const uint64_t v = wsum[q];
-        if (q < wv) before += v;
-        total += v;
-    }
     uint64_t *tab = reinterpret_cast<uint64_t *>(dst + 64);
-    uint64_t run = before + incl - mine;
-    for (uint32_t k = k0; k < k1; ++k) {
-        tab[k] = run;
-        run += info[k].x;
+    uint64_t total = 0;   // sizes of the rounds before
+    for (uint32_t base = 0; base < n; base += nt * R) {
+        const uint32_t k0 = base + t * R;
+        uint32_t v[R];
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) v[r] = k0 + r < n ? info[k0 + r].x : 0u;
+        uint64_t mine = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) mine += v[r];
+        uint64_t incl = mine;
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint64_t o = (uint64_t)__shfl_up((unsigned long long)incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        uint64_t before = 0, round = 0;
+        for (uint32_t q = 0; q < nw; ++q) {
+            const uint64_t x = wsum[q];
+            if (q < wv) before += x;
+            round += x;
+        }
+        __syncthreads();   // wsum is rewritten by the next round
+        uint64_t run = total + before + incl - mine;
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) {
+            if (k0 + r < n) tab[k0 + r] = run;
+            run += v[r];
+        }
+        total += round;
     }
     if (t == 0) tab[n] = total;
     if (t < 16) {
