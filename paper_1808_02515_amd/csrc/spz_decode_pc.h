@@ -5,7 +5,7 @@
 // the decoding work only the forecaster recurrence is serial (Section 5.4
 // names the dependence of each prediction on the previous sample as the
 // limit). A workgroup holds the segments of 64 column chains and splits into
-// a three-stage pipeline of wavefronts over chunks of 8 blocks, one barrier
+// a four-stage pipeline of wavefronts over chunks of 8 blocks, one barrier
 // per step:
 //
 //   parser (chunk t)       stage   the loads of chunk t, issued a step
@@ -18,7 +18,9 @@
 //                          issue   16-byte loads of chunk t+1's header and
 //                                  payload windows (their bases come from the
 //                                  parse), in flight over the rest of the step
-//   NP unpackers (t-1)     an aligned two-dword LDS read and a funnel shift
+//   NP unpackers (t-3)     rows of chunk t-3 (the consumer's image) to
+//                          global memory, 16-byte stores
+//                (t-1)     an aligned two-dword LDS read and a funnel shift
 //                          give 32 bits = 32/w fields: lanes = (segment,
 //                          block, 32/w adjacent columns) for row-major
 //                          payloads, one read per row; (segment, block,
@@ -33,11 +35,15 @@
 //                          serial chain); sgn(e) * delta_prev is summed on odd
 //                          rows and the accumulator saturates once per block
 //                          (practical FIRE, Section 4.2.2). Samples go to an
-//                          LDS image of the chunk's rows, which leaves with
-//                          16-byte stores.
+//                          LDS image of the chunk's rows, written over the
+//                          error buffers the consumer has just read.
 //
-// Staging windows, records and error buffers are double buffered by chunk
-// parity, so each stage reads what the one before wrote a step earlier.
+// Staging windows, records and error buffers (with the row images) are
+// double buffered by chunk parity, so each stage reads what the one before
+// wrote a step earlier. This pipelined form serves single containers with
+// D >= 7; the producer/consumer form below (producers that parse, stage and
+// unpack their own segments, a consumer that also stores the rows) serves
+// smaller D and every batched decode.
 //
 // A block inside a run of zero blocks decodes as a block whose errors are
 // all 0 (reading R9: the prediction alone; sgn(0) = 0 leaves the FIRE
@@ -70,9 +76,9 @@ __host__ __device__ constexpr uint32_t pc_spw(uint32_t D, uint32_t NP, uint32_t 
 // the workgroup's (segment, candidate record) pairs (D >= 7); with more passes
 // the parser becomes the longest stage (measured: D = 1, 2, 3, 6 decode
 // slower, D = 4 level). The batched kernel keeps the producer/consumer form
-// (NP producers, NC consumers) at every D: its smaller LDS and register
-// footprint keeps four workgroups on a CU where the pipelined form fits three,
-// and batched throughput follows the number of consumer chains in flight.
+// (NP producers, NC consumers) at every D: batched throughput follows the
+// VALU work per sample, which the separate parser wave raises (measured on a
+// 10,000-stream batch: 2.12 against 2.23 TB/s with the pipelined form).
 __host__ __device__ constexpr bool pc_pipe(uint32_t D) {
     return pc_spw(D, kPcProducers, kPcConsumers) * kPcChunkBlocks <= 64;
 }
