@@ -691,10 +691,25 @@ __device__ __forceinline__ void pc_decode_group_pipe(uint32_t nchunks, Init init
     const bool st_on = lane < LPS * SPW;
     const uint32_t st_s = min(lane / LPS, SPW - 1), st_k = lane % LPS;
     u32x4 reg[SP2];
+    // A staging lane's segment: its source and extent are fixed; its window
+    // bases change with every chunk. Where the staging lanes of a segment
+    // are its parse lanes (one parse pass, 64 / SPW = CB lanes per segment),
+    // every such lane keeps the segment's parse state (next record, cursor,
+    // pending run blocks, window bases) in registers, since each parse leaves
+    // the new state in all of the segment's lanes; otherwise the parse and
+    // the staging read it back from the segment state in LDS.
+    constexpr bool BASES_IN_REGS = LPS == CB && G::PPPASS == 1;
+    const uint8_t *st_src = nullptr;
+    uint32_t st_ext = 0, nx_hb = 0, nx_pb = 0;
+    uint32_t ps_r = 0, ps_cur = 0, ps_rle = 0, ps_nrow = 0, ps_nrec = 0, ps_ok = 0;
     auto stage_issue = [&]() {
-        const PcSeg &sg = SEG[st_s];
-        const uint8_t *const src = sg.src;
-        const uint32_t ext = sg.ok ? sg.ext : 0u, hbase = sg.hbase, pbase = sg.pbase;
+        uint32_t hbase = nx_hb, pbase = nx_pb;
+        if (!BASES_IN_REGS) {
+            hbase = SEG[st_s].hbase;
+            pbase = SEG[st_s].pbase;
+        }
+        const uint8_t *const src = st_src;
+        const uint32_t ext = st_ext;
 #pragma unroll
         for (uint32_t t = 0; t < SP2; ++t) {
             const uint32_t k = st_k + LPS * t;
@@ -716,6 +731,13 @@ __device__ __forceinline__ void pc_decode_group_pipe(uint32_t nchunks, Init init
     if (parser) {
         if (lane < SPW) init(SEG[lane], lane);
         wave_sync();
+        const PcSeg &sg = SEG[st_s];
+        st_src = sg.src;
+        st_ext = sg.ok ? sg.ext : 0u;
+        nx_hb = sg.hbase;
+        nx_pb = sg.pbase;
+        ps_r = sg.r; ps_cur = sg.cursor; ps_rle = sg.rle_rem;
+        ps_nrow = sg.nrow; ps_nrec = sg.nrec; ps_ok = sg.ok;
         stage_issue();
     }
     __syncthreads();
@@ -746,7 +768,15 @@ __device__ __forceinline__ void pc_decode_group_pipe(uint32_t nchunks, Init init
                 const uint32_t sl = pr / CB, k = pr % CB;
                 const uint32_t s = min(sl, SPW - 1);
                 const bool here = pr < G::PPAIRS;
-                const PcSeg sg = SEG[s];   // one read of the chunk's state
+                // the segment's state at the chunk's start (one LDS read, or
+                // none: see BASES_IN_REGS)
+                struct { uint32_t r, cursor, rle_rem, nrec, nrow, hbase, pbase, ok; } sg;
+                if (BASES_IN_REGS) {
+                    sg = {ps_r, ps_cur, ps_rle, ps_nrec, ps_nrow, nx_hb, nx_pb, ps_ok};
+                } else {
+                    const PcSeg q = SEG[s];
+                    sg = {q.r, q.cursor, q.rle_rem, q.nrec, q.nrow, q.hbase, q.pbase, q.ok};
+                }
                 const uint32_t nbk = sg.nrow >> 3;
                 const uint32_t bic = c * CB < nbk ? min((uint32_t)CB, nbk - c * CB) : 0u;
                 const uint32_t rr = sg.r + k;
@@ -785,6 +815,14 @@ __device__ __forceinline__ void pc_decode_group_pipe(uint32_t nchunks, Init init
                 const uint32_t cov = sg.rle_rem + pc_total<CB>(used ? nb : 0u);
                 const uint32_t nbad = pc_total<CB>(badk ? 1u : 0u);
                 const uint32_t r1 = sg.r + n_used, cur1 = sg.cursor + adv;
+                if (BASES_IN_REGS) {
+                    // this lane's segment is its staging segment (s == st_s)
+                    nx_hb = (4 + ((r1 * D * HB) >> 3)) & ~15u;
+                    nx_pb = cur1 & ~15u;
+                    ps_r = r1;
+                    ps_cur = cur1;
+                    ps_rle = cov > bic ? cov - bic : 0u;
+                }
                 wave_sync();
                 if (here && k == 0) {
                     PcSeg &ns = SEG[s];
