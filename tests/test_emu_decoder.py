@@ -8,8 +8,10 @@ launch the library would make is run.
 It covers the one-segment form of the 65,536-sample int8 walk, the case kept
 off the GPU (test_gpu_parity.py): the current decoder decodes it exactly with
 no access outside its buffers. It also decodes a random corpus of oracle
-containers (both decoders: the producer/consumer one for D <= 16, the walker
-for grouped headers and D up to 80) and corrupted containers, which may only
+containers (every decoder: the pipelined form for D = 7..16 and the
+producer/consumer form for smaller D in the single-container kernel, the
+batched kernel's producer/consumer form for every D <= 16, the walker for
+grouped headers and D up to 80) and corrupted containers, which may only
 change samples or set the status word."""
 import os
 import shutil
